@@ -1,0 +1,206 @@
+"""ctypes binding of the FP64 oracle (``glbm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Arrays use the
+oracle's layout: populations ``[q][y][x]`` with ``q = b*(2Lx+1) + a``,
+velocity ``(a - Lx, b - Ly)``; node fields ``[y][x]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+BC_PERIODIC = 0
+BC_WALL = 1
+BC_EQ_ENDS = 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "glbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB):
+            build_oracle(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.orc_equilibrium_1d.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        lib.orc_equilibrium_1d.restype = None
+        lib.orc_step_probabilities.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        lib.orc_step_probabilities.restype = None
+        lib.orc_tau_from_kn.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.orc_tau_from_kn.restype = ctypes.c_double
+        lib.orc_create.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double,
+        ]
+        lib.orc_create.restype = ctypes.c_void_p
+        lib.orc_destroy.argtypes = [ctypes.c_void_p]
+        lib.orc_tau.argtypes = [ctypes.c_void_p]
+        lib.orc_tau.restype = ctypes.c_double
+        lib.orc_omega.argtypes = [ctypes.c_void_p]
+        lib.orc_omega.restype = ctypes.c_double
+        lib.orc_time.argtypes = [ctypes.c_void_p]
+        lib.orc_time.restype = ctypes.c_int64
+        lib.orc_nvel.argtypes = [ctypes.c_void_p]
+        lib.orc_nvel.restype = ctypes.c_int
+        lib.orc_tables.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        lib.orc_init_fields.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        lib.orc_init_populations.argtypes = [ctypes.c_void_p, _dp]
+        lib.orc_get_populations.argtypes = [ctypes.c_void_p, _dp]
+        lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        lib.orc_moments.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_stats.argtypes = [ctypes.c_void_p, _dp]
+        _lib = lib
+        return lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a, n=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+def equilibrium_1d(N: int, u: float, c: float = 1.0, theta0: float | None = None) -> np.ndarray:
+    """Closed-form equilibrium (Eq. maineq03) at rho = 1 for n = -N..N.
+
+    ``theta0`` defaults to the calibration N c^2 / 3 of Eq. maineq05."""
+    lib = _load()
+    if theta0 is None:
+        theta0 = N * c * c / 3.0
+    out = np.zeros(2 * N + 1)
+    lib.orc_equilibrium_1d(int(N), float(c), float(theta0), float(u), _ptr(out))
+    return out
+
+
+def step_probabilities(N: int, u: float, c: float = 1.0, theta0: float | None = None) -> np.ndarray:
+    """(P-, P0, P+) of Eq. maineq04."""
+    lib = _load()
+    if theta0 is None:
+        theta0 = N * c * c / 3.0
+    out = np.zeros(3)
+    lib.orc_step_probabilities(int(N), float(c), float(theta0), float(u), _ptr(out))
+    return out
+
+
+def rest_weights(N: int) -> np.ndarray:
+    """Equilibrium at rho = 1, u = 0 (the weights W_n used by the force term)."""
+    return equilibrium_1d(N, 0.0)
+
+
+def tau_from_kn(kn: float, H: float, theta: float) -> float:
+    return _load().orc_tau_from_kn(float(kn), float(H), float(theta))
+
+
+class OracleSolver:
+    """One FP64 solver instance (see ``glbm_oracle.c`` for the step order)."""
+
+    STAT_NAMES = (
+        "mass", "momentum_x", "momentum_y", "energy_post", "residual",
+        "wall_mass_bottom", "wall_mass_top", "wall_momentum_bottom", "wall_momentum_top",
+        "nonpositive_nodes",
+    )
+
+    def __init__(self, dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0,
+                 bc_x=BC_PERIODIC, bc_y=BC_PERIODIC, wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0):
+        self._lib = _load()
+        wu = np.asarray(wall_u, dtype=np.float64)
+        er = np.asarray(end_rho, dtype=np.float64)
+        h = self._lib.orc_create(int(dims), int(level_x), int(level_y), int(nx), int(ny),
+                                 float(tau), float(kn), int(bc_x), int(bc_y), _ptr(wu), _ptr(er), float(g))
+        if not h:
+            raise ValueError("oracle rejected the configuration")
+        self._h = h
+        self.dims = int(dims)
+        self.level_x = int(level_x)
+        self.level_y = int(level_y) if dims == 2 else 0
+        self.nx = int(nx)
+        self.ny = int(ny) if dims == 2 else 1
+        self.Q = self._lib.orc_nvel(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_destroy(h)
+            self._h = None
+
+    @property
+    def tau(self):
+        return self._lib.orc_tau(self._h)
+
+    @property
+    def omega(self):
+        return self._lib.orc_omega(self._h)
+
+    @property
+    def time(self):
+        return self._lib.orc_time(self._h)
+
+    @property
+    def nodes(self):
+        return self.nx * self.ny
+
+    def tables(self):
+        Wx = np.zeros(2 * self.level_x + 1)
+        Wy = np.zeros(2 * self.level_y + 1)
+        jp = np.zeros(1)
+        self._lib.orc_tables(self._h, _ptr(Wx), _ptr(Wy), _ptr(jp))
+        return Wx, Wy, float(jp[0])
+
+    def init_fields(self, rho=None, ux=None, uy=None):
+        n = self.nodes
+        r, a, b = _f64(rho, n), _f64(ux, n), _f64(uy, n)
+        self._lib.orc_init_fields(self._h, _ptr(r), _ptr(a), _ptr(b))
+
+    def init_populations(self, f0):
+        f0 = _f64(f0, self.Q * self.nodes)
+        self._lib.orc_init_populations(self._h, _ptr(f0))
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros(self.Q * self.nodes)
+        self._lib.orc_get_populations(self._h, _ptr(out))
+        return out.reshape(self.Q, self.ny, self.nx)
+
+    def step(self, n: int = 1):
+        self._lib.orc_step(self._h, int(n))
+
+    def moments(self) -> dict:
+        n = self.nodes
+        out = {k: np.zeros(n) for k in ("rho", "ux", "uy", "T", "pxy")}
+        self._lib.orc_moments(self._h, *[_ptr(out[k]) for k in ("rho", "ux", "uy", "T", "pxy")])
+        return {k: v.reshape(self.ny, self.nx) for k, v in out.items()}
+
+    def stats(self) -> dict:
+        out = np.zeros(len(self.STAT_NAMES))
+        self._lib.orc_stats(self._h, _ptr(out))
+        return dict(zip(self.STAT_NAMES, out.tolist()))

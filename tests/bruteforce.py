@@ -1,0 +1,115 @@
+"""Literal push-form stepper for tiny lattices (test-only).
+
+An independent second reading of one time step, written without numpy and
+without the oracle: dictionaries keyed by (x, y, c_x, c_y), the equilibrium
+obtained by enumerating the 3^N outcomes of the dice problem of section 2,
+collision at every node (Eq. maineq01, linear force of section 5.4), then
+each post-collision population *pushed* to x + c.  Populations pushed
+through a diffuse wall are absorbed per destination column and re-emitted as
+the unit-density equilibrium at the wall velocity scaled so that the column
+keeps its mass; populations pushed out of a fixed-equilibrium end are lost
+and the end supplies equilibrium populations at rest.
+"""
+from __future__ import annotations
+
+import itertools
+from collections import defaultdict
+
+PERIODIC, WALL, EQ_ENDS = 0, 1, 2
+
+
+def dice_law(N: int, u: float) -> dict:
+    """Sum of N steps in {-1, 0, 1} with mean u/N and variance (N/3)/N each."""
+    if N == 0:
+        return {0: 1.0}
+    mean = u / N
+    second = (N / 3.0) / N + mean * mean
+    p = {1: 0.5 * (second + mean), -1: 0.5 * (second - mean)}
+    p[0] = 1.0 - p[1] - p[-1]
+    law = defaultdict(float)
+    for steps in itertools.product((-1, 0, 1), repeat=N):
+        prob = 1.0
+        for s in steps:
+            prob *= p[s]
+        law[sum(steps)] += prob
+    return dict(law)
+
+
+def run(dims, Lx, Ly, nx, ny, omega, g, bc_x, bc_y, wall_u, end_rho, f0, steps):
+    """Advance ``f0`` (a dict {(x, y, cx, cy): value}) by ``steps`` steps."""
+    if dims == 1:
+        Ly, ny, bc_y = 0, 1, PERIODIC
+    vel = [(cx, cy) for cy in range(-Ly, Ly + 1) for cx in range(-Lx, Lx + 1)]
+    Wx, Wy = dice_law(Lx, 0.0), dice_law(Ly, 0.0)
+    thx = Lx / 3.0
+    jplus = sum(cy * Wy[cy] for cy in range(1, Ly + 1))
+    Fbot, Ftop = dice_law(Lx, wall_u[0]), dice_law(Lx, wall_u[1])
+    f = dict(f0)
+    for _ in range(steps):
+        post = {}
+        for x in range(nx):
+            for y in range(ny):
+                rho = sum(f[(x, y, cx, cy)] for cx, cy in vel)
+                ux = sum(f[(x, y, cx, cy)] * cx for cx, cy in vel) / rho
+                uy = sum(f[(x, y, cx, cy)] * cy for cx, cy in vel) / rho
+                ex, ey = dice_law(Lx, ux), dice_law(Ly, uy)
+                for cx, cy in vel:
+                    v = f[(x, y, cx, cy)]
+                    feq = rho * ex[cx] * ey[cy]
+                    force = Wx[cx] * Wy[cy] * cx * g / thx
+                    post[(x, y, cx, cy)] = v + omega * (feq - v) + force
+        new = {}
+        absorbed = {"bot": defaultdict(float), "top": defaultdict(float)}
+        for (x, y, cx, cy), v in post.items():
+            xd, yd = x + cx, y + cy
+            if bc_y == WALL and yd < 0:
+                absorbed["bot"][xd % nx] += v
+                continue
+            if bc_y == WALL and yd >= ny:
+                absorbed["top"][xd % nx] += v
+                continue
+            yd %= ny
+            if bc_x == EQ_ENDS and not (0 <= xd < nx):
+                continue
+            new[(xd % nx, yd, cx, cy)] = v
+        if bc_y == WALL:
+            for x in range(nx):
+                for cx, cy in vel:
+                    if cy > 0:
+                        for y in range(cy):
+                            new[(x, y, cx, cy)] = absorbed["bot"][x] / jplus * Fbot[cx] * Wy[cy]
+                    elif cy < 0:
+                        for y in range(ny + cy, ny):
+                            new[(x, y, cx, cy)] = absorbed["top"][x] / jplus * Ftop[cx] * Wy[cy]
+        if bc_x == EQ_ENDS:
+            for y in range(ny):
+                for cx, cy in vel:
+                    for x in range(0, min(cx, nx)):
+                        new[(x, y, cx, cy)] = end_rho[0] * Wx[cx] * Wy[cy]
+                    for x in range(max(nx + cx, 0), nx):
+                        new[(x, y, cx, cy)] = end_rho[1] * Wx[cx] * Wy[cy]
+        assert len(new) == len(vel) * nx * ny
+        f = new
+    return f
+
+
+def to_dict(arr, Lx, Ly):
+    """[q][y][x] array (q = b*(2Lx+1) + a) -> dict keyed by (x, y, cx, cy)."""
+    Q, ny, nx = arr.shape
+    out = {}
+    for q in range(Q):
+        b, a = divmod(q, 2 * Lx + 1)
+        for y in range(ny):
+            for x in range(nx):
+                out[(x, y, a - Lx, b - Ly)] = float(arr[q, y, x])
+    return out
+
+
+def from_dict(d, Lx, Ly, nx, ny):
+    import numpy as np
+
+    Qx, Qy = 2 * Lx + 1, 2 * Ly + 1
+    arr = np.zeros((Qx * Qy, ny, nx))
+    for (x, y, cx, cy), v in d.items():
+        arr[(cy + Ly) * Qx + (cx + Lx), y, x] = v
+    return arr

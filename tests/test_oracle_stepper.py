@@ -1,0 +1,240 @@
+"""Pins of the oracle's time stepping (Eq. maineq01, walls, force, ends).
+
+* an independent push-form brute-force stepper on tiny lattices;
+* invariants: mass, momentum (and its exact balance with force and walls);
+* omega = 0 streaming is a pure permutation (bitwise return);
+* a uniform equilibrium is a fixed point;
+* free-molecular Couette flow (omega = 0) reaches a closed-form state;
+* a small shear wave decays at the rate nu k^2 with nu = theta tau
+  (sections 5.1/5.2: nu = theta tau for the collision frequency 1/(tau + 1/2)).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04597_amd import workloads as wl
+from tests import bruteforce as bf
+
+
+def _rand_state(seed, Q, ny, nx):
+    return wl.random_populations(seed, Q, nx, ny).astype(np.float64)
+
+
+CASES = [
+    # dims, Lx, Ly, nx, ny, tau, g, bc_x, bc_y, wall_u, end_rho
+    (1, 1, 0, 7, 1, 0.8, 0.0, bf.PERIODIC, bf.PERIODIC, (0, 0), (1, 1)),
+    (1, 2, 0, 7, 1, 0.3, 1e-3, bf.PERIODIC, bf.PERIODIC, (0, 0), (1, 1)),
+    (1, 3, 0, 9, 1, 1.7, 0.0, bf.EQ_ENDS, bf.PERIODIC, (0, 0), (1.0, 0.125)),
+    (1, 3, 0, 2, 1, 0.9, 0.0, bf.PERIODIC, bf.PERIODIC, (0, 0), (1, 1)),   # |c| > nx: double wrap
+    (2, 1, 1, 5, 6, 0.7, 2e-3, bf.PERIODIC, bf.PERIODIC, (0, 0), (1, 1)),
+    (2, 2, 2, 3, 8, 1.1, 1e-3, bf.PERIODIC, bf.WALL, (-0.05, 0.08), (1, 1)),
+    (2, 3, 3, 3, 6, 0.6, 5e-4, bf.PERIODIC, bf.WALL, (0.1, -0.1), (1, 1)),
+    (2, 3, 2, 2, 5, 2.0, 0.0, bf.PERIODIC, bf.WALL, (0.03, 0.0), (1, 1)),  # mixed levels, nx < Lx
+    (2, 2, 1, 6, 3, 0.9, 0.0, bf.EQ_ENDS, bf.PERIODIC, (0, 0), (1.2, 0.9)),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_oracle_matches_bruteforce_push_stepper(case):
+    dims, Lx, Ly, nx, ny, tau, g, bcx, bcy, wu, er = case
+    Q = (2 * Lx + 1) * (2 * Ly + 1)
+    f0 = _rand_state(11 + Lx + nx, Q, ny, nx)
+    steps = 12
+    s = oracle.OracleSolver(dims, Lx, Ly, nx, ny, tau=tau, bc_x=bcx, bc_y=bcy, wall_u=wu, end_rho=er, g=g)
+    s.init_populations(f0)
+    s.step(steps)
+    got = s.populations()
+    ref = bf.run(dims, Lx, Ly, nx, ny, 1.0 / (tau + 0.5), g, bcx, bcy, wu, er, bf.to_dict(f0, Lx, Ly), steps)
+    want = bf.from_dict(ref, Lx, Ly, nx, ny)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-15)
+
+
+def test_mass_conserved_with_walls_and_force():
+    s = oracle.OracleSolver(2, 3, 3, 5, 16, tau=0.9, bc_y=oracle.BC_WALL, wall_u=(-0.1, 0.07), g=1e-3)
+    f0 = _rand_state(3, 49, 16, 5)
+    s.init_populations(f0)
+    m0 = f0.sum()
+    for _ in range(10):
+        s.step(20)
+        assert abs(s.stats()["mass"] - m0) <= 1e-13 * m0
+
+
+def test_momentum_conserved_periodic_and_force_adds_g():
+    for g in (0.0, 2e-4):
+        s = oracle.OracleSolver(2, 2, 2, 6, 7, tau=0.7, g=g)
+        s.init_populations(_rand_state(5, 25, 7, 6))
+        p0 = s.stats()["momentum_x"]
+        py0 = s.stats()["momentum_y"]
+        s.step(40)
+        st = s.stats()
+        assert st["momentum_x"] == pytest.approx(p0 + 40 * 42 * g, abs=1e-13)
+        assert st["momentum_y"] == pytest.approx(py0, abs=1e-13)
+
+
+def test_wall_momentum_balance_every_step():
+    """P(t+1) - P(t) = g * nodes - (momentum given to both walls in that streaming)."""
+    nx, ny, g = 3, 12, 3e-4
+    s = oracle.OracleSolver(2, 3, 3, nx, ny, tau=1.3, bc_y=oracle.BC_WALL, wall_u=(-0.08, 0.05), g=g)
+    s.init_populations(_rand_state(9, 49, ny, nx))
+    for _ in range(15):
+        st = s.stats()
+        s.step(1)
+        st1 = s.stats()
+        lhs = st1["momentum_x"] - st["momentum_x"]
+        rhs = g * nx * ny - st["wall_momentum_bottom"] - st["wall_momentum_top"]
+        assert lhs == pytest.approx(rhs, abs=1e-13)
+        # the absorbed mass is re-emitted: mass is unchanged
+        assert st1["mass"] == pytest.approx(st["mass"], rel=1e-14)
+
+
+@pytest.mark.parametrize("dims,Lx,Ly,nx,ny", [(1, 3, 0, 5, 1), (2, 2, 2, 3, 4), (2, 3, 1, 4, 6)])
+def test_free_streaming_is_a_permutation(dims, Lx, Ly, nx, ny):
+    """omega = 0, periodic: after lcm(nx, ny) steps the state returns bitwise."""
+    Q = (2 * Lx + 1) * (2 * Ly + 1)
+    s = oracle.OracleSolver(dims, Lx, Ly, nx, ny, tau=math.inf)
+    assert s.omega == 0.0
+    f0 = _rand_state(4, Q, ny, nx)
+    s.init_populations(f0)
+    period = math.lcm(nx, ny)
+    s.step(period - 1)
+    assert not np.array_equal(s.populations(), f0)
+    s.step(1)
+    assert np.array_equal(s.populations(), f0)
+
+
+def test_uniform_equilibrium_is_fixed_point():
+    rho, ux, uy = 1.3, 0.04, -0.02
+    s = oracle.OracleSolver(2, 3, 3, 4, 5, tau=0.8)
+    s.init_fields(np.full(20, rho), np.full(20, ux), np.full(20, uy))
+    f0 = s.populations().copy()
+    s.step(25)
+    np.testing.assert_allclose(s.populations(), f0, rtol=1e-13)
+    # walls at rest and a fluid at rest: also a fixed point
+    w = oracle.OracleSolver(2, 2, 2, 3, 9, tau=0.8, bc_y=oracle.BC_WALL)
+    w.init_fields()
+    f1 = w.populations().copy()
+    w.step(30)
+    np.testing.assert_allclose(w.populations(), f1, rtol=1e-13)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_free_molecular_couette_closed_form(N):
+    """omega = 0 Couette flow from rest.  Wall densities stay 1 and, once every
+    moving population has crossed the channel (t >= ny), populations with
+    c_y > 0 are the bottom-wall equilibrium, c_y < 0 the top-wall one and
+    c_y = 0 the rest weights: u_x = 0, rho = 1, Pxy = -2 U J+,
+    T = theta + (1 - W_0) U^2 / 2."""
+    nx, ny, U = 3, 10, 0.07
+    s = oracle.OracleSolver(2, N, N, nx, ny, tau=math.inf, bc_y=oracle.BC_WALL, wall_u=(-U, U))
+    s.init_fields()
+    s.step(ny + 2)
+    Wx, Wy, jplus = s.tables()
+    theta = N / 3.0
+    m = s.moments()
+    np.testing.assert_allclose(m["rho"], 1.0, atol=1e-14)
+    np.testing.assert_allclose(m["ux"], 0.0, atol=1e-15)
+    np.testing.assert_allclose(m["pxy"], -2 * U * jplus, rtol=1e-12)
+    np.testing.assert_allclose(m["T"], theta + (1 - Wy[N]) * U * U / 2, rtol=1e-13)
+    st = s.stats()
+    # the bottom wall (moving at -U) absorbs populations emitted by the top wall
+    # (mean x velocity +U) and re-emits them at -U: it takes up +2 U J+ of x
+    # momentum per column and step, the top wall the opposite
+    assert st["wall_momentum_bottom"] == pytest.approx(2 * U * jplus * nx, rel=1e-12)
+    assert st["wall_momentum_top"] == pytest.approx(-2 * U * jplus * nx, rel=1e-12)
+    # the half flux approaches that of a Maxwellian, sqrt(theta / (2 pi)), as N grows
+    assert jplus < math.sqrt(theta / (2 * math.pi))
+
+
+def test_half_flux_ratio_increases_with_level():
+    ratios = []
+    for N in range(1, 8):
+        s = oracle.OracleSolver(2, N, N, 1, 2 * N, tau=1.0, bc_y=oracle.BC_WALL)
+        _, _, jp = s.tables()
+        ratios.append(jp / math.sqrt((N / 3.0) / (2 * math.pi)))
+    assert all(ratios[i] < ratios[i + 1] < 1.0 for i in range(6))
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_shear_wave_decay_rate(N):
+    """u_x = A sin(k y) on a periodic lattice decays as exp(-nu k^2 t), nu = theta tau,
+    up to O(k^2) lattice corrections."""
+    nx, ny, tau, A = 1, 64, 0.6, 1e-4
+    s = oracle.OracleSolver(2, N, N, nx, ny, tau=tau)
+    k = 2 * math.pi / ny
+    y = np.arange(ny)
+    s.init_fields(np.ones(ny), A * np.sin(k * y), np.zeros(ny))
+    s.step(50)
+    a0 = float((s.moments()["ux"][:, 0] * np.sin(k * y)).sum())
+    s.step(400)
+    a1 = float((s.moments()["ux"][:, 0] * np.sin(k * y)).sum())
+    rate = -math.log(a1 / a0) / 400
+    nu = (N / 3.0) * tau
+    assert rate == pytest.approx(nu * k * k, rel=0.02)
+
+
+def test_sod_mass_constant_until_disturbance_reaches_ends():
+    """Fixed equilibrium ends: in- and out-flux balance while the end nodes stay at rest."""
+    N, n = 3, 120
+    s = oracle.OracleSolver(1, N, 0, n, 1, kn=0.01, bc_x=oracle.BC_EQ_ENDS, end_rho=(1.0, 0.125))
+    rho0 = wl.sod_density(n, 1.0, 0.125).astype(np.float64)
+    s.init_fields(rho0)
+    m0 = rho0.sum()
+    for _ in range(6):
+        s.step(3)
+        assert s.stats()["mass"] == pytest.approx(m0, rel=1e-14)
+
+
+def test_kn_mapping_of_the_configs():
+    """tau from Eq. kn with H = ny (walls) or the tube length (Sod)."""
+    sod = oracle.OracleSolver(1, 3, 0, 2000, 1, kn=0.01, bc_x=oracle.BC_EQ_ENDS)
+    assert sod.tau == pytest.approx(0.01 * 2000 / math.sqrt(2.0), rel=1e-14)
+    c = oracle.OracleSolver(2, 3, 3, 4, 256, kn=1.0, bc_y=oracle.BC_WALL)
+    assert c.tau == pytest.approx(256 / math.sqrt(2.0), rel=1e-14)
+    assert c.omega == pytest.approx(1.0 / (c.tau + 0.5), rel=1e-15)
+
+
+def test_poiseuille_balance_and_continuum_limit():
+    """Force-driven channel at steady state: the wall uptake balances the force,
+    the profile is symmetric, and as Kn -> 0 the centre-line speed tends to the
+    Navier-Stokes value U0 = F H^2 / (8 rho nu) of section 5.4 with an excess
+    that is first order in Kn (wall slip)."""
+    N, nx, ny, g = 1, 1, 24, 1e-6
+    excess = []
+    for kn in (0.02, 0.01):
+        s = oracle.OracleSolver(2, N, N, nx, ny, kn=kn, bc_y=oracle.BC_WALL, g=g)
+        s.init_fields()
+        nu = (N / 3.0) * s.tau
+        s.step(int(8 * ny * ny / nu))
+        st = s.stats()
+        assert st["residual"] < 1e-10
+        uptake = st["wall_momentum_bottom"] + st["wall_momentum_top"]
+        assert uptake == pytest.approx(g * nx * ny, rel=1e-8)
+        u = s.moments()["ux"][:, 0]
+        np.testing.assert_allclose(u, u[::-1], rtol=1e-9)
+        excess.append(u.max() / (g * ny * ny / (8 * nu)) - 1.0)
+    assert 0.0 < excess[1] < 0.06
+    assert 0.4 < excess[1] / excess[0] < 0.6
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_moments_of_equilibrium_state(N):
+    """At f = f^eq(rho, u) every reported moment is fixed: the density and
+    velocity given, temperature theta = N/3 per degree of freedom (orders 0-2
+    of the equilibrium are Maxwellian, section 2) and zero shear moment
+    (product form of section 4)."""
+    nx, ny = 5, 3
+    rho, ux, uy = wl.random_fields(21, nx, ny, rho_amp=0.2, u_amp=0.2)
+    s = oracle.OracleSolver(2, N, N, nx, ny, tau=0.7)
+    s.init_fields(rho, ux, uy)
+    m = s.moments()
+    np.testing.assert_allclose(m["rho"], rho, rtol=1e-14)
+    np.testing.assert_allclose(m["ux"], ux, atol=1e-15)
+    np.testing.assert_allclose(m["uy"], uy, atol=1e-15)
+    np.testing.assert_allclose(m["T"], N / 3.0, rtol=1e-13)
+    np.testing.assert_allclose(m["pxy"], 0.0, atol=1e-15)
+    one = oracle.OracleSolver(1, N, 0, nx, 1, tau=0.7)
+    one.init_fields(rho[0], ux[0])
+    m1 = one.moments()
+    np.testing.assert_allclose(m1["T"], N / 3.0, rtol=1e-13)
