@@ -1,0 +1,209 @@
+"""Benchmark of the fused stream-collide step on one MI355X.
+
+Workload (default): force-driven Poiseuille channel, tensor-product
+G-D2Q(11x11) (level N = 5 per axis, k = 4, 121 velocities), 4096 x 1024
+nodes, diffuse walls at rest, g = 1e-5, Kn = 0.1, FP32 populations; inputs are
+resident in HBM before the timed region.  One "step" is one time step of the
+whole lattice (one launch of the fused kernel).
+
+Prints ONE JSON line: GLUPS (1e9 node updates per second), the roofline of
+the step kernel (algorithmic bytes 2 Q s per node update over the average
+launch duration, against the 8 TB/s HBM peak), an optional per-level sweep and
+the FP64 oracle timed on the host cores over a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--storage f32|bf16_shifted_sr|...]
+                    [--no-sweep] [--no-cpu-baseline] [--copy-probe]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+ELEM_BYTES = {"f32": 4, "f32_shifted": 4, "bf16_shifted": 2, "bf16_shifted_sr": 2}
+DTYPE = {"f32": "f32", "f32_shifted": "f32", "bf16_shifted": "bf16", "bf16_shifted_sr": "bf16"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_poiseuille_d2q121_4096x1024.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("glbm_device.h", "glbm_inst.hip", "glbm_api.hip"):
+        with open(os.path.join(ROOT, "paper_1905_04597_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_steps(solver, steps: int, warmup: int):
+    """Warm up, then time exactly `steps` launches with events on the solver's stream."""
+    import torch
+
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(solver.stream)
+    t0 = time.perf_counter()
+    solver.step(steps)
+    stop.record(solver.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / 1e3, wall
+
+
+def run_gpu(level: int, nx: int, ny: int, storage: str, steps: int, warmup: int):
+    from paper_1905_04597_amd import glbm
+    from paper_1905_04597_amd import workloads as wl
+
+    w = wl.poiseuille(nx=nx, ny=ny, level=level, storage=storage)
+    s = glbm.solver_for(w)
+    s.init_fields()
+    gpu_s, wall_s = time_steps(s, steps, warmup)
+    nodes = nx * ny
+    Q = (2 * level + 1) ** 2
+    per_step = gpu_s / steps
+    algo_bytes = 2 * Q * ELEM_BYTES[storage] * nodes
+    out = {
+        "level": level, "k": level - 1, "Q": Q, "glups": nodes * steps / gpu_s / 1e9,
+        "ms_per_step": per_step * 1e3, "achieved_GBs": algo_bytes / per_step / 1e9,
+        "bytes_per_launch": algo_bytes, "wall_s": wall_s,
+    }
+    st = s.stats()
+    out["mass_drift_rel"] = abs(st["mass"] - nodes) / nodes
+    s.close()
+    return out
+
+
+def copy_probe(nbytes: int = 2 << 30, reps: int = 10):
+    """A plain device copy of known size: the achievable read + write rate on
+    this GPU (context for the roofline) and a known-size kernel for
+    calibrating the memory counters."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        b.copy_(a)
+    stop.record()
+    torch.cuda.synchronize()
+    sec = start.elapsed_time(stop) / 1e3 / reps
+    return {"bytes_each_way": nbytes, "reps": reps, "GBs": round(2 * nbytes / sec / 1e9, 1)}
+
+
+def cpu_baseline(level: int = 5, nx: int = 64, ny: int = 1024, steps: int = 40):
+    """The FP64 oracle (single-threaded C) on a bounded sample of the workload:
+    the same level, wall distance and parameters, a narrower channel."""
+    import oracle
+
+    s = oracle.OracleSolver(2, level, level, nx, ny, kn=0.1, bc_y=oracle.BC_WALL, g=1e-5)
+    s.init_fields()
+    s.step(1)
+    t0 = time.perf_counter()
+    s.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": nx * ny * steps / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+            "sample": "G-D2Q(11x11) Poiseuille %dx%d (same ny, walls, g, Kn), %d steps, %.1f s, "
+                      "single-threaded FP64 C" % (nx, ny, steps, dt)}
+
+
+def load_traffic(storage: str):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = t.get(storage)
+    if not rec or t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=sorted(ELEM_BYTES))
+    ap.add_argument("--level", type=int, default=5)
+    ap.add_argument("--nx", type=int, default=4096)
+    ap.add_argument("--ny", type=int, default=1024)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    a = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the hot path is a single-GPU lattice update "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    torch.cuda.set_device(0)
+    copy = copy_probe(reps=10 if not a.copy_probe else 20)
+    main_run = run_gpu(a.level, a.nx, a.ny, a.storage, a.steps, a.warmup)
+    sweep = None
+    if not a.no_sweep:
+        sweep = []
+        for lv in range(1, 8):
+            r = run_gpu(lv, a.nx, a.ny, a.storage, a.sweep_steps, 5)
+            sweep.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
+                          if k in ("k", "Q", "glups", "achieved_GBs", "ms_per_step")})
+            sweep[-1]["frac"] = round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(a.level)
+    achieved = main_run["achieved_GBs"]
+    line = {
+        "metric": "GLUPS (Poiseuille G-D2Q(11x11) 4096x1024 stream-collide) and % HBM roofline",
+        "value": round(main_run["glups"], 4),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[a.storage],
+        "data": "synthetic",
+        "config": {
+            "workload": "force-driven Poiseuille, G-D2Q(%dx%d) (k=%d), %dx%d nodes, diffuse walls, "
+                        "g=1e-5, Kn=0.1, from rest" % (2 * a.level + 1, 2 * a.level + 1, a.level - 1, a.nx, a.ny),
+            "storage": a.storage,
+            "nodes": a.nx * a.ny,
+            "velocities": main_run["Q"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": load_traffic(a.storage),
+            "bytes_per_launch": main_run["bytes_per_launch"],
+            "copy_kernel_GBs": copy["GBs"],
+        },
+        "cpu_baseline": cpu,
+        "mass_drift_rel": main_run["mass_drift_rel"],
+    }
+    if sweep is not None:
+        line["per_k"] = sweep
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

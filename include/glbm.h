@@ -1,0 +1,161 @@
+/*
+ * glbm: Gaussian lattice Boltzmann hierarchy on MI355X (gfx950).
+ *
+ * C-ABI of the HIP library libglbm.so.  The library advances the models of
+ * O. Ilyin, "Gaussian Lattice Boltzmann method and its applications to
+ * rarefied flows" (arXiv:1905.04597): the G-D1Q(2N+1) models of section 2
+ * (update Eq. maineq01, equilibrium Eqs. maineq02-maineq06 = the N-fold
+ * convolution of the D1Q3 equilibrium at velocity u/N) and their tensor
+ * products in two dimensions (section 4), with the linear body force of
+ * section 5.4, diffuse-reflection walls (sections 5.3, 5.4) and fixed
+ * equilibrium ends (section 5.1).
+ *
+ * Units are lattice units: time step 1 and lattice spacing 1 on each axis,
+ * so a level-N axis has velocities -N..N and temperature theta = N/3
+ * (Eq. maineq05 with c = 1).  Velocities are reported in these units.
+ *
+ * Conventions shared by every entry point:
+ *  - Velocity index q = b * (2 Nx + 1) + a for the velocity (a - Nx, b - Ny),
+ *    Nx, Ny the levels of the two axes (one dimension: Ny = 0, q = a).
+ *  - Canonical arrays (fields and FP32 populations exchanged with the
+ *    caller) are row-major [y][x] per field and [q][y][x] for populations,
+ *    x fastest, no padding.
+ *  - All pointers passed to the library are DEVICE pointers on the device
+ *    that was current when glbm_create was called, unless stated otherwise.
+ *    The caller owns them (PyTorch allocations in the Python binding) and
+ *    keeps them alive while the handle uses them.
+ *  - Work is enqueued on the caller's HIP stream, asynchronously, unless an
+ *    entry point says that it synchronizes.
+ *  - Every call returns GLBM_OK (0) or a negative error code; the message of
+ *    the last failure on the calling thread is glbm_last_error().  No C++
+ *    exception crosses this interface.
+ *
+ * Time convention: after glbm_init_* the solver is at time t = 0 with
+ * pre-collision populations f(0); each glbm_step advances t by one
+ * (collision, then streaming, Eq. maineq01).  glbm_moments and
+ * glbm_get_populations report the pre-collision state f(t).
+ */
+#ifndef GLBM_H
+#define GLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define GLBM_OK 0
+#define GLBM_ERR_INVALID (-1)     /* invalid argument or configuration */
+#define GLBM_ERR_UNSUPPORTED (-2) /* valid but not built (level, storage, boundary combination) */
+#define GLBM_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define GLBM_ERR_STATE (-4)       /* call out of order (e.g. step before init) */
+
+/* Boundary kinds. */
+#define GLBM_BC_PERIODIC 0
+#define GLBM_BC_WALL 1    /* diffuse-reflection wall (y axis, two dimensions) */
+#define GLBM_BC_EQ_ENDS 2 /* fixed equilibrium ends at rest (x axis) */
+
+/* Population storage. */
+#define GLBM_STORE_F32 0          /* f in FP32 */
+#define GLBM_STORE_F32_SHIFTED 1  /* f - S in FP32: S is the rest state W_a W_b rounded to
+                                     multiples of 2^-24 with unit sum (deviation storage) */
+#define GLBM_STORE_BF16_SHIFTED 2 /* f - S in BF16, round to nearest even */
+#define GLBM_STORE_BF16_SHIFTED_SR 3 /* f - S in BF16, stochastic rounding keyed by
+                                        (time step, node, velocity): reproducible */
+
+/* Largest hierarchy level per axis built into the library. */
+#define GLBM_MAX_LEVEL 7
+
+typedef struct glbm_config {
+    int32_t dims;     /* 1 or 2 */
+    int32_t level_x;  /* hierarchy level N of the x axis: 2N+1 velocities, 1..GLBM_MAX_LEVEL */
+    int32_t level_y;  /* level of the y axis (two dimensions), 1..GLBM_MAX_LEVEL; ignored in 1D */
+    int32_t storage;  /* GLBM_STORE_* */
+    int64_t nx, ny;   /* nodes per axis; ny is ignored (1) in one dimension */
+    double tau;       /* relaxation time (> 0), or <= 0 to derive it from kn */
+    double kn;        /* Knudsen number of Eq. kn: tau = kn H / sqrt(2 theta), with
+                         H = ny and theta = level_y / 3 in two dimensions (walls half
+                         way between nodes), H = nx and theta = level_x / 3 in one */
+    int32_t bc_x;     /* GLBM_BC_PERIODIC or GLBM_BC_EQ_ENDS */
+    int32_t bc_y;     /* GLBM_BC_PERIODIC or GLBM_BC_WALL (two dimensions) */
+    double wall_u[2]; /* x velocity of the bottom (y = -1/2) and top (y = ny - 1/2) walls */
+    double end_rho[2];/* densities of the left (x < 0) and right (x >= nx) equilibrium ends */
+    double g;         /* body force along x: momentum added per node and step */
+} glbm_config;
+
+/* Global diagnostics, FP64 sums over all nodes (glbm_stats). */
+typedef struct glbm_stats {
+    int64_t time;           /* t */
+    double mass;            /* sum of f(t) */
+    double momentum_x;      /* sum of f(t) c_x (pre-collision) */
+    double momentum_y;      /* sum of f(t) c_y */
+    double energy_post;     /* sum of f*(t) |c|^2 after the collision of step t (the model
+                               is isothermal: reported, not conserved) */
+    double residual;        /* ||u_x(t) - u_x(t-1)||_2 / ||u_x(t)||_2; NaN at t = 0 */
+    double wall_mass[2];    /* mass absorbed (and re-emitted) by the bottom/top wall in the
+                               streaming from t to t+1 */
+    double wall_momentum[2];/* x momentum given to the bottom/top wall in that streaming */
+    double nonpositive_nodes; /* nodes with |u| above sqrt(2 N theta) on some axis
+                                 (equilibrium not positive, section 3) */
+} glbm_stats_t;
+
+typedef struct glbm_solver glbm_t;
+
+/* Bytes of ONE population buffer for cfg (the library's internal layout:
+ * [q][y][x + halo] with ghost columns), or 0 if cfg is invalid.  The caller
+ * allocates two such buffers on the device (for HBM-budget admission this is
+ * the whole device footprint apart from a few KB of tables). */
+size_t glbm_population_bytes(const glbm_config *cfg);
+
+/* Create a solver over caller-owned device buffers pop_a and pop_b, each of
+ * glbm_population_bytes(cfg) bytes, 256-byte aligned, on HIP stream `stream`
+ * (hipStream_t; NULL = the default stream).  The state is undefined until
+ * glbm_init_fields or glbm_init_populations.  *out receives the handle.
+ * Errors: GLBM_ERR_INVALID for a bad configuration (including omega outside
+ * (0, 2), ny < 2 Ny with walls, walls combined with equilibrium ends, a
+ * buffer above 4 GiB), GLBM_ERR_UNSUPPORTED for level combinations not built. */
+int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, glbm_t **out);
+
+/* f(0) = f^eq(rho, u) at every node (Eqs. maineq02-maineq06 per axis, product
+ * form of section 4).  rho, ux, uy: device float arrays [ny][nx]; NULL means
+ * rho = 1, u = 0.  Sets t = 0. */
+int glbm_init_fields(glbm_t *h, const float *rho, const float *ux, const float *uy);
+
+/* f(0) given: device float array [Q][ny][nx] of pre-collision populations.
+ * Sets t = 0. */
+int glbm_init_populations(glbm_t *h, const float *f0);
+
+/* Advance nsteps >= 0 time steps (each: moments, equilibrium, BGK collision
+ * with force, wall densities, pull streaming; one fused kernel per step). */
+int glbm_step(glbm_t *h, int64_t nsteps);
+
+/* Moments of f(t): density, velocity, temperature per degree of freedom
+ * T = (sum f |c|^2 / rho - |u|^2) / dims and shear moment
+ * Pxy = sum f c_x c_y - rho u_x u_y.  Device float arrays [ny][nx]; any may
+ * be NULL (skipped). */
+int glbm_moments(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *pxy);
+
+/* Copy f(t) (pre-collision, FP32, canonical [Q][ny][nx]) into device memory. */
+int glbm_get_populations(glbm_t *h, float *out);
+
+/* Global FP64 diagnostics at the current time.  Synchronizes the stream. */
+int glbm_stats(glbm_t *h, glbm_stats_t *out);
+
+/* Derived parameters: relaxation time, collision frequency 1/(tau + 1/2),
+ * number of velocities, current time.  Host pointers; any may be NULL. */
+int glbm_info(const glbm_t *h, double *tau, double *omega, int32_t *nvel, int64_t *time);
+
+/* Release the handle (host state and the library's small device tables).
+ * Caller-owned buffers are not touched.  Waits for the handle's stream. */
+int glbm_destroy(glbm_t *h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *glbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLBM_H */

@@ -1,0 +1,90 @@
+"""Build libglbm.so for gfx950 with hipcc (in-tree).
+
+Usage: python -m paper_1905_04597_amd.build [--jobs J] [--incremental]
+
+Every hierarchy level is compiled as its own object (they are the slow
+part), in parallel, and linked into ``paper_1905_04597_amd/libglbm.so``.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libglbm.so")
+ARCH = "gfx950"
+LEVELS = (7, 6, 5, 4, 3, 2, 1, 0)  # slowest first; 0 = mixed-level lattices
+
+FLAGS = [
+    "-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
+    # keep the compiler from emitting packed FP32 arithmetic
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def _hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def _deps():
+    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))] + [
+        os.path.join(os.path.dirname(HERE), "include", "glbm.h")
+    ]
+
+
+def _stale(obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps())
+
+
+def _compile(args):
+    src, obj, defines = args
+    cmd = [_hipcc(), *FLAGS, *defines, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr[-4000:]))
+    return obj
+
+
+def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    tasks = [(os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), [])]
+    for lv in LEVELS:
+        tasks.append((os.path.join(CSRC, "glbm_inst.hip"), os.path.join(BUILD, "glbm_inst_%d.o" % lv),
+                      ["-DGLBM_LEVEL=%d" % lv]))
+    todo = [t for t in tasks if not incremental or _stale(t[1])]
+    jobs = jobs or min(len(todo) or 1, os.cpu_count() or 4, 16)
+    if todo:
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            for obj in ex.map(_compile, todo):
+                if verbose:
+                    print("built", os.path.relpath(obj, HERE), flush=True)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [t[1] for t in tasks]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true")
+    a = ap.parse_args(argv)
+    print(build(a.jobs, a.incremental, verbose=True))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,406 @@
+// C-ABI of libglbm.so (declared in include/glbm.h): configuration checks,
+// run-time tables, buffer bookkeeping and kernel dispatch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "../../include/glbm.h"
+#include "glbm_internal.h"
+
+using namespace glbm;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(GLBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+Variant g_variants[kMaxLevel + 1][kMaxLevel + 1][4][3][2];
+std::once_flag g_once;
+
+void register_all()
+{
+    register_level_1();
+    register_level_2();
+    register_level_3();
+    register_level_4();
+    register_level_5();
+    register_level_6();
+    register_level_7();
+    register_mixed();
+}
+
+// Host copy of the per-axis equilibrium at rho = 1 (N-fold convolution of the
+// D1Q3 equilibrium at u/N, lattice units), in double, for the wall tables.
+void host_axis_equilibrium(int N, double u, double *F)
+{
+    double cur[kMaxQ1] = {1.0};
+    int len = 1;
+    const double v = u / N;
+    const double pp = 1.0 / 6.0 + 0.5 * v + 0.5 * v * v;
+    const double pm = 1.0 / 6.0 - 0.5 * v + 0.5 * v * v;
+    const double p0 = 2.0 / 3.0 - v * v;
+    for (int k = 0; k < N; ++k) {
+        double nxt[kMaxQ1] = {};
+        for (int i = 0; i < len; ++i) {
+            nxt[i] += pm * cur[i];
+            nxt[i + 1] += p0 * cur[i];
+            nxt[i + 2] += pp * cur[i];
+        }
+        len += 2;
+        for (int i = 0; i < len; ++i) cur[i] = nxt[i];
+    }
+    for (int i = 0; i < 2 * N + 1; ++i) F[i] = cur[i];
+}
+
+struct Geometry {
+    int lx, ly, q, eb;
+    int64_t nx, ny, nxp;
+    uint64_t plane_bytes, buf_bytes;
+};
+
+int check_config(const glbm_config *c, Geometry *g)
+{
+    if (!c) return fail(GLBM_ERR_INVALID, "config is NULL");
+    if (c->dims != 1 && c->dims != 2) return fail(GLBM_ERR_INVALID, "dims must be 1 or 2 (got %d)", c->dims);
+    const int lx = c->level_x, ly = c->dims == 2 ? c->level_y : 0;
+    if (lx < 1 || lx > kMaxLevel) return fail(GLBM_ERR_INVALID, "level_x must be in 1..%d", kMaxLevel);
+    if (c->dims == 2 && (ly < 1 || ly > kMaxLevel)) return fail(GLBM_ERR_INVALID, "level_y must be in 1..%d", kMaxLevel);
+    if (c->storage < GLBM_STORE_F32 || c->storage > GLBM_STORE_BF16_SHIFTED_SR)
+        return fail(GLBM_ERR_INVALID, "unknown storage %d", c->storage);
+    const int64_t nx = c->nx, ny = c->dims == 2 ? c->ny : 1;
+    if (nx < 1 || ny < 1) return fail(GLBM_ERR_INVALID, "nx and ny must be positive");
+    if (c->bc_x != GLBM_BC_PERIODIC && c->bc_x != GLBM_BC_EQ_ENDS)
+        return fail(GLBM_ERR_INVALID, "bc_x must be periodic or equilibrium ends");
+    const int bcy = c->dims == 2 ? c->bc_y : GLBM_BC_PERIODIC;
+    if (bcy != GLBM_BC_PERIODIC && bcy != GLBM_BC_WALL)
+        return fail(GLBM_ERR_INVALID, "bc_y must be periodic or wall");
+    if (c->bc_x == GLBM_BC_EQ_ENDS && bcy == GLBM_BC_WALL)
+        return fail(GLBM_ERR_INVALID, "walls and equilibrium ends cannot be combined");
+    if (bcy == GLBM_BC_WALL && ny < 2 * ly)
+        return fail(GLBM_ERR_INVALID, "ny (%lld) must be at least 2*level_y with walls", (long long)ny);
+    if (c->dims == 2 && bcy == GLBM_BC_PERIODIC && ny < ly)
+        return fail(GLBM_ERR_INVALID, "periodic ny (%lld) must be at least level_y", (long long)ny);
+    if (c->bc_x == GLBM_BC_EQ_ENDS && nx < lx)
+        return fail(GLBM_ERR_INVALID, "nx must be at least level_x with equilibrium ends");
+    g->lx = lx;
+    g->ly = ly;
+    g->q = (2 * lx + 1) * (2 * ly + 1);
+    g->eb = (c->storage == GLBM_STORE_BF16_SHIFTED || c->storage == GLBM_STORE_BF16_SHIFTED_SR) ? 2 : 4;
+    g->nx = nx;
+    g->ny = ny;
+    g->nxp = (kGhost + nx + lx + 63) / 64 * 64;  // node x at column kGhost + x
+    g->plane_bytes = (uint64_t)(ny * g->nxp) * g->eb;
+    g->buf_bytes = (g->plane_bytes * g->q + 255) & ~(uint64_t)255;
+    if (nx * ny > (int64_t)0x7fffffff / 4) return fail(GLBM_ERR_INVALID, "too many nodes");
+    if (g->buf_bytes >= ((uint64_t)1 << 32))
+        return fail(GLBM_ERR_INVALID, "population buffer of %llu bytes exceeds 4 GiB", (unsigned long long)g->buf_bytes);
+    return GLBM_OK;
+}
+
+// Seed of the stochastic rounding for the step that produces time t.
+uint32_t step_seed(int64_t t)
+{
+    uint64_t x = (uint64_t)t * 0x9e3779b97f4a7c15ULL + 0x632be59bd9b4e019ULL;
+    x ^= x >> 31;
+    x *= 0xbf58476d1ce4e5b9ULL;
+    x ^= x >> 29;
+    return (uint32_t)(x >> 32);
+}
+
+__global__ void reduce_partials(const double *partials, int nblocks, double *out)
+{
+    __shared__ double red[kBlock];
+    for (int k = 0; k < kNumStats; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(size_t)b * kNumStats + k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+namespace glbm {
+Variant *variant_slot(int lx, int ly, int storage, int bcx, int bcy)
+{
+    return &g_variants[lx][ly][storage][bcx][bcy];
+}
+}  // namespace glbm
+
+struct glbm_solver {
+    glbm_config cfg;
+    Geometry geo;
+    double tau, omega;
+    void *buf[2];
+    int cur;  // index of the buffer holding f*(t); the other holds f*(t-1) or f(0)
+    int64_t t;
+    bool ready;
+    hipStream_t stream;
+    const Variant *var;
+    KArgs base;
+    int grid;
+    double *d_partials, *d_out, *h_out;
+    int device;
+};
+
+extern "C" {
+
+const char *glbm_last_error(void) { return g_error.c_str(); }
+
+size_t glbm_population_bytes(const glbm_config *cfg)
+{
+    Geometry g;
+    if (check_config(cfg, &g) != GLBM_OK) return 0;
+    return (size_t)g.buf_bytes;
+}
+
+int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, glbm_t **out)
+{
+    if (!out) return fail(GLBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    Geometry g;
+    int rc = check_config(cfg, &g);
+    if (rc != GLBM_OK) return rc;
+    if (!pop_a || !pop_b || pop_a == pop_b) return fail(GLBM_ERR_INVALID, "two distinct population buffers are required");
+    if (((uintptr_t)pop_a & 255) || ((uintptr_t)pop_b & 255)) return fail(GLBM_ERR_INVALID, "buffers must be 256-byte aligned");
+
+    double tau = cfg->tau;
+    if (!(tau > 0.0)) {
+        const double H = cfg->dims == 2 ? (double)g.ny : (double)g.nx;
+        const double theta = (cfg->dims == 2 ? g.ly : g.lx) / 3.0;
+        if (!(cfg->kn > 0.0)) return fail(GLBM_ERR_INVALID, "either tau > 0 or kn > 0 is required");
+        tau = cfg->kn * H / sqrt(2.0 * theta);  // Eq. kn with nu = theta tau
+    }
+    const double omega = 1.0 / (tau + 0.5);
+    if (!(omega > 0.0 && omega < 2.0)) return fail(GLBM_ERR_INVALID, "collision frequency %g outside (0, 2)", omega);
+
+    std::call_once(g_once, register_all);
+    const int bcy = cfg->dims == 2 ? cfg->bc_y : GLBM_BC_PERIODIC;
+    const Variant *v = variant_slot(g.lx, g.ly, cfg->storage, cfg->bc_x, bcy);
+    if (!v->step)
+        return fail(GLBM_ERR_UNSUPPORTED, "no kernels built for levels (%d, %d) with these boundaries", g.lx, g.ly);
+
+    glbm_solver *h = new (std::nothrow) glbm_solver();
+    if (!h) return fail(GLBM_ERR_INVALID, "out of host memory");
+    h->cfg = *cfg;
+    h->geo = g;
+    h->tau = tau;
+    h->omega = omega;
+    h->buf[0] = pop_a;
+    h->buf[1] = pop_b;
+    h->cur = 0;
+    h->t = 0;
+    h->ready = false;
+    h->stream = (hipStream_t)stream;
+    h->var = v;
+    (void)hipGetDevice(&h->device);
+
+    const int64_t nodes = g.nx * g.ny;
+    h->grid = (int)((nodes + kBlock - 1) / kBlock);
+    KArgs &a = h->base;
+    memset(&a, 0, sizeof a);
+    a.buf_bytes = (uint32_t)g.buf_bytes;
+    a.plane_bytes = (uint32_t)g.plane_bytes;
+    a.nx = (int32_t)g.nx;
+    a.ny = (int32_t)g.ny;
+    a.nxp = (int32_t)g.nxp;
+    a.nodes = (int32_t)nodes;
+    a.remap = 1;
+    a.omega = (float)omega;
+    a.gth = (float)(cfg->g / (g.lx / 3.0));  // force shape W_a c_a g / theta_x
+    a.g = (float)cfg->g;
+    // wall emission: unit-density equilibrium at the wall speed (x) times the
+    // rest weights (y), in FP32; the kernels divide the absorbed mass by the
+    // mass these FP32 tables emit, so that each column keeps its mass
+    double F[kMaxQ1];
+    for (int side = 0; side < 2; ++side) {
+        const double U = bcy == GLBM_BC_WALL ? cfg->wall_u[side] : 0.0;
+        host_axis_equilibrium(g.lx, U, F);
+        double sum = 0.0;
+        for (int i = 0; i < 2 * g.lx + 1; ++i) {
+            a.fw[side][i] = (float)F[i];
+            sum += (double)a.fw[side][i];
+        }
+        a.fwsum[side] = sum;
+        a.uw[side] = (float)U;
+    }
+
+    hipError_t e = hipMalloc((void **)&h->d_partials, sizeof(double) * kNumStats * (size_t)h->grid);
+    if (e == hipSuccess) e = hipMalloc((void **)&h->d_out, sizeof(double) * kNumStats);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_out, sizeof(double) * kNumStats, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipFree(h->d_partials);
+        (void)hipFree(h->d_out);
+        delete h;
+        return hip_fail(e, "allocating statistics buffers");
+    }
+    *out = h;
+    return GLBM_OK;
+}
+
+static int do_init(glbm_t *h, const float *rho, const float *ux, const float *uy, const float *f0)
+{
+    if (!h) return fail(GLBM_ERR_INVALID, "handle is NULL");
+    KArgs a = h->base;
+    hipError_t e;
+    if (h->cfg.bc_x == GLBM_BC_EQ_ENDS) {
+        a.dst = h->buf[0];
+        a.dst2 = h->buf[1];
+        const int n = h->geo.q * (int)h->geo.ny * 2 * h->geo.lx;
+        e = h->var->ends(a, (n + kBlock - 1) / kBlock, (float)h->cfg.end_rho[0], (float)h->cfg.end_rho[1], h->stream);
+        if (e != hipSuccess) return hip_fail(e, "launching the end-state fill");
+    }
+    a.dst = h->buf[0];   // f*(0)
+    a.dst2 = h->buf[1];  // f(0)
+    a.i_rho = rho;
+    a.i_ux = ux;
+    a.i_uy = uy;
+    a.i_f = f0;
+    a.seed = step_seed(0);
+    e = h->var->init(a, h->grid, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the init kernel");
+    h->cur = 0;
+    h->t = 0;
+    h->ready = true;
+    return GLBM_OK;
+}
+
+int glbm_init_fields(glbm_t *h, const float *rho, const float *ux, const float *uy)
+{
+    return do_init(h, rho, ux, uy, nullptr);
+}
+
+int glbm_init_populations(glbm_t *h, const float *f0)
+{
+    if (!f0) return fail(GLBM_ERR_INVALID, "f0 is NULL");
+    return do_init(h, nullptr, nullptr, nullptr, f0);
+}
+
+int glbm_step(glbm_t *h, int64_t nsteps)
+{
+    if (!h) return fail(GLBM_ERR_INVALID, "handle is NULL");
+    if (!h->ready) return fail(GLBM_ERR_STATE, "step before init");
+    if (nsteps < 0) return fail(GLBM_ERR_INVALID, "nsteps must be >= 0");
+    KArgs a = h->base;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        a.src = h->buf[h->cur];
+        a.dst = h->buf[1 - h->cur];
+        a.seed = step_seed(h->t + 1);
+        hipError_t e = h->var->step(a, h->grid, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "launching the step kernel");
+        h->cur = 1 - h->cur;
+        h->t += 1;
+    }
+    return GLBM_OK;
+}
+
+static int observe(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *pxy, float *f)
+{
+    if (!h) return fail(GLBM_ERR_INVALID, "handle is NULL");
+    if (!h->ready) return fail(GLBM_ERR_STATE, "moments before init");
+    KArgs a = h->base;
+    // f(t) is the pull of f*(t-1) (t >= 1) or the stored f(0) itself (t = 0);
+    // both live in the buffer that the next step will overwrite.
+    a.src = h->buf[1 - h->cur];
+    a.local = h->t == 0;
+    a.o_rho = rho;
+    a.o_ux = ux;
+    a.o_uy = uy;
+    a.o_T = T;
+    a.o_pxy = pxy;
+    a.o_f = f;
+    hipError_t e = h->var->observe(a, h->grid, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the observe kernel");
+    return GLBM_OK;
+}
+
+int glbm_moments(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *pxy)
+{
+    return observe(h, rho, ux, uy, T, pxy, nullptr);
+}
+
+int glbm_get_populations(glbm_t *h, float *out)
+{
+    if (!out) return fail(GLBM_ERR_INVALID, "out is NULL");
+    return observe(h, nullptr, nullptr, nullptr, nullptr, nullptr, out);
+}
+
+int glbm_stats(glbm_t *h, glbm_stats_t *out)
+{
+    if (!h || !out) return fail(GLBM_ERR_INVALID, "NULL argument");
+    if (!h->ready) return fail(GLBM_ERR_STATE, "stats before init");
+    KArgs a = h->base;
+    a.src = h->buf[h->cur];
+    a.prev = h->t > 0 ? h->buf[1 - h->cur] : nullptr;
+    a.partials = h->d_partials;
+    hipError_t e = h->var->stats(a, h->grid, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the stats kernel");
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kBlock), 0, h->stream, h->d_partials, h->grid, h->d_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "launching the reduction");
+    e = hipMemcpyAsync(h->h_out, h->d_out, sizeof(double) * kNumStats, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the statistics");
+    const double *s = h->h_out;
+    out->time = h->t;
+    out->mass = s[0];
+    out->momentum_x = s[1];
+    out->momentum_y = s[2];
+    out->energy_post = s[3];
+    out->residual = h->t > 0 ? sqrt(s[5]) / sqrt(s[4]) : NAN;
+    out->wall_mass[0] = s[6];
+    out->wall_momentum[0] = s[7];
+    out->wall_mass[1] = s[8];
+    out->wall_momentum[1] = s[9];
+    out->nonpositive_nodes = s[10];
+    return GLBM_OK;
+}
+
+int glbm_info(const glbm_t *h, double *tau, double *omega, int32_t *nvel, int64_t *time)
+{
+    if (!h) return fail(GLBM_ERR_INVALID, "handle is NULL");
+    if (tau) *tau = h->tau;
+    if (omega) *omega = h->omega;
+    if (nvel) *nvel = h->geo.q;
+    if (time) *time = h->t;
+    return GLBM_OK;
+}
+
+int glbm_destroy(glbm_t *h)
+{
+    if (!h) return GLBM_OK;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->d_partials);
+    (void)hipFree(h->d_out);
+    (void)hipHostFree(h->h_out);
+    delete h;
+    return GLBM_OK;
+}
+
+}  // extern "C"

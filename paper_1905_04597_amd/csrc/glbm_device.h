@@ -1,0 +1,801 @@
+// Device code of the Gaussian lattice Boltzmann hierarchy for gfx950.
+//
+// One lane owns one lattice node and keeps all Q populations of that node in
+// registers for the whole step:
+//   pull (Eq. maineq01 streaming, read side) -> moments (section 2) ->
+//   per-axis equilibrium = N-fold convolution of the D1Q3 equilibrium at
+//   u/N (Eqs. maineq02-maineq06 in lattice units) -> tensor product
+//   (section 4) -> BGK relaxation with collision frequency 1/(tau + 1/2)
+//   plus the linear force of section 5.4 -> store.
+//
+// Memory layout of a population buffer: velocity planes [q][y][xp] with rows
+// of nxp padded columns (a multiple of 64); node x lives at column x + G,
+// G = 64, so that a wave of 64 nodes reads and writes whole, aligned cache
+// lines of its own row.  The LX columns on each side of the interior are
+// ghosts.  With periodic x every store of an edge node is replicated into the
+// matching ghost columns, so a pull never wraps: the source of velocity c_x
+// sits at a constant byte shift from the node, which the buffer loads take as
+// an immediate offset.  With fixed equilibrium ends the ghosts hold the end
+// state and are never written.
+//
+// Tables that depend only on the level (rest weights, half flux, force
+// shape) are compile-time constants folded into the instructions; tables
+// that depend on run-time parameters (wall emission at the wall speed) are
+// kernel arguments, uniform across the wave and held in scalar registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace glbm {
+
+constexpr int kMaxLevel = 7;
+constexpr int kMaxQ1 = 2 * kMaxLevel + 1;
+constexpr int kBlock = 256;
+constexpr int kNumStats = 11;
+constexpr int kGhost = 64;  // padded column of node x = 0 (>= the largest level)
+
+enum StorageKind { ST_F32 = 0, ST_F32S = 1, ST_BF16S = 2, ST_BF16SR = 3 };
+enum BcX { BCX_PERIODIC = 0, BCX_EQ = 2 };
+enum BcY { BCY_PERIODIC = 0, BCY_WALL = 1 };
+
+// ---------------------------------------------------------------- tables
+// Rest weights of a level-N axis: the equilibrium at rho = 1, u = 0, i.e.
+// the coefficients of (1/6 z^-1 + 2/3 + 1/6 z)^N (N-fold sum of D1Q3 at
+// rest, section 2 and Appendix A), computed in double at compile time and
+// made exactly symmetric.
+template <int N>
+struct RestWeights {
+    double w[2 * N + 1];
+    constexpr RestWeights() : w{}
+    {
+        double cur[2 * kMaxLevel + 1] = {};
+        cur[0] = 1.0;
+        int len = 1;
+        for (int k = 0; k < N; ++k) {
+            double nxt[2 * kMaxLevel + 1] = {};
+            for (int i = 0; i < len; ++i) {
+                nxt[i] += cur[i] / 6.0;
+                nxt[i + 1] += cur[i] * (2.0 / 3.0);
+                nxt[i + 2] += cur[i] / 6.0;
+            }
+            len += 2;
+            for (int i = 0; i < len; ++i) cur[i] = nxt[i];
+        }
+        for (int i = 0; i <= N; ++i) w[i] = w[2 * N - i] = cur[i];
+    }
+};
+
+template <int N>
+inline constexpr RestWeights<N> kRest{};
+
+// Half flux J+ = sum_{n>0} n W_n of the FP32-rounded rest weights (exact sum).
+template <int N>
+constexpr double half_flux_f32()
+{
+    double s = 0.0;
+    for (int n = 1; n <= N; ++n) s += n * (double)(float)kRest<N>.w[N + n];
+    return s;
+}
+
+// The shift of the shifted storages is snapped to the 2^-24 grid (exact in
+// FP32 below 1) with the centre entry absorbing the remainder, so that it sums
+// to exactly one: rho = 1 + sum of deviations is then exact and the FP32
+// collision carries no systematic mass error, only unbiased rounding.  (The
+// shift is only an offset; tables that stand for physical weights keep full
+// relative FP32 precision instead.)
+constexpr double kGrid = 16777216.0;  // 2^24
+
+constexpr long long snap(double w) { return (long long)(w * kGrid + 0.5); }
+
+// Shift of the shifted storages: S_ab ~ W_a W_b on the grid, symmetric,
+// summing exactly to 1; plus the moments of S that the kernels add back.
+template <int LX, int LY>
+struct ShiftTable {
+    static constexpr int QX = 2 * LX + 1, QY = 2 * LY + 1;
+    float s[QY][QX];
+    float sxx, syy;        // sum S c_x^2, sum S c_y^2
+    float absorbed;        // sum of S over the populations one wall absorbs per column
+    constexpr ShiftTable() : s{}, sxx(0.0f), syy(0.0f), absorbed(0.0f)
+    {
+        long long q[QY][QX] = {};
+        long long tot = 0;
+        for (int b = 0; b < QY; ++b)
+            for (int a = 0; a < QX; ++a) tot += (q[b][a] = snap(kRest<LX>.w[a] * kRest<LY>.w[b]));
+        q[LY][LX] += (long long)kGrid - tot;
+        long long xx = 0, yy = 0, ab = 0;
+        for (int b = 0; b < QY; ++b)
+            for (int a = 0; a < QX; ++a) {
+                const long long ca = a - LX, cb = b - LY;
+                xx += q[b][a] * ca * ca;
+                yy += q[b][a] * cb * cb;
+                if (cb < 0) ab += q[b][a] * (-cb);
+                s[b][a] = (float)(q[b][a] / kGrid);
+            }
+        sxx = (float)(xx / kGrid);
+        syy = (float)(yy / kGrid);
+        absorbed = (float)(ab / kGrid);
+    }
+};
+
+template <int LX, int LY>
+inline constexpr ShiftTable<LX, LY> kShift{};
+
+// ------------------------------------------------------- unroll helper
+template <int I, int E, class F>
+__device__ __forceinline__ void unroll_from(F &&f)
+{
+    if constexpr (I < E) {
+        f(std::integral_constant<int, I>{});
+        unroll_from<I + 1, E>(f);
+    }
+}
+template <int E, class F>
+__device__ __forceinline__ void unroll(F &&f)
+{
+    unroll_from<0, E>(f);
+}
+
+// ------------------------------------------------------------- storage
+template <int ST>
+struct Elem;
+template <>
+struct Elem<ST_F32> {
+    static constexpr int bytes = 4;
+    static constexpr bool shifted = false;
+};
+template <>
+struct Elem<ST_F32S> {
+    static constexpr int bytes = 4;
+    static constexpr bool shifted = true;
+};
+template <>
+struct Elem<ST_BF16S> {
+    static constexpr int bytes = 2;
+    static constexpr bool shifted = true;
+};
+template <>
+struct Elem<ST_BF16SR> {
+    static constexpr int bytes = 2;
+    static constexpr bool shifted = true;
+};
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    // raw buffer (stride 0), gfx9-family dword 3
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int ST>
+__device__ __forceinline__ float ld(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (Elem<ST>::bytes == 2) {
+        auto raw = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        return __builtin_bit_cast(float, ((uint32_t)__builtin_bit_cast(unsigned short, raw)) << 16);
+    } else {
+        // the builtin returns the raw 32 bits as an integer
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+}
+
+// Store one value; `rnd` is 32 random bits for the stochastic rounding mode.
+template <int ST>
+__device__ __forceinline__ void st(rsrc_t r, uint32_t voff, uint32_t soff, float v, uint32_t rnd = 0)
+{
+    if constexpr (ST == ST_BF16S) {
+        const __bf16 h = (__bf16)v;  // round to nearest even (v_cvt_pk_bf16_f32)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, 0);
+    } else if constexpr (ST == ST_BF16SR) {
+        // stochastic rounding in hardware (v_cvt_sr_bf16_f32): unbiased, so
+        // increments far below one bf16 ulp still accumulate on average
+        bf16x2_t h = {};
+        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)__builtin_bit_cast(uint32_t, h), r, voff, soff, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    }
+}
+
+// 32-bit integer mixer (xor-shift-multiply, "lowbias32" constants).
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// Random bits of population q at a node whose hash is h: a rotation of h
+// (distinct 32-bit windows for q mod 32), decorrelated across groups of 32.
+template <int q>
+__device__ __forceinline__ uint32_t rnd_of(uint32_t h)
+{
+    constexpr uint32_t rot = q & 31;
+    uint32_t r = rot ? __builtin_amdgcn_alignbit(h, h, rot) : h;
+    if constexpr ((q >> 5) != 0) r ^= (uint32_t)(q >> 5) * 0x9e3779b9U;
+    return r;
+}
+
+// The value a 16-bit storage keeps of v (same rounding as st()).
+template <int ST>
+__device__ __forceinline__ float quantize(float v, uint32_t rnd)
+{
+    if constexpr (ST == ST_BF16S) {
+        const __bf16 h = (__bf16)v;
+        return __builtin_bit_cast(float, (uint32_t)__builtin_bit_cast(unsigned short, h) << 16);
+    } else if constexpr (ST == ST_BF16SR) {
+        bf16x2_t h = {};
+        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
+        return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, h) << 16);
+    } else {
+        return v;
+    }
+}
+
+// ------------------------------------------------------------ kernel args
+struct KArgs {
+    const void *src;      // pull source: post-collision f*(t-1) (or f(0) in local mode)
+    void *dst;            // destination of f*(t)
+    uint32_t buf_bytes;   // bytes of one population buffer
+    uint32_t plane_bytes; // bytes of one velocity plane (ny * nxp elements)
+    int32_t nx, ny, nxp;  // nodes per axis, padded row length (multiple of 64, >= G + nx + LX)
+    int32_t nodes;        // nx * ny
+    int32_t remap;        // XCD-aware block order
+    int32_t local;        // observe kernel: read f(t) at the node, no streaming
+    uint32_t seed;        // per-step seed of the stochastic rounding
+    float omega;          // 1 / (tau + 1/2)
+    float gth;            // g / theta_x
+    float fw[2][kMaxQ1];  // F_a(U_wall) at unit density (FP32), bottom / top wall
+    double fwsum[2];      // sum_a fw_a of the FP32 table (exact, in double)
+    // observe outputs (canonical [y][x] / [q][y][x], may be null)
+    float *o_rho, *o_ux, *o_uy, *o_T, *o_pxy, *o_f;
+    // stats
+    const void *prev;     // f*(t-1) for the residual (null at t = 0)
+    float g;
+    float uw[2];          // wall velocities
+    double *partials;     // [gridDim][kNumStats]
+    // init
+    const float *i_rho, *i_ux, *i_uy, *i_f;
+    void *dst2;           // init: buffer receiving f(0)
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of tiles so that the halo lines two neighbouring tiles share
+// meet in the same L2.
+__device__ __forceinline__ int tile_index(const KArgs &p)
+{
+    const int b = blockIdx.x, G = gridDim.x;
+    if (!p.remap) return b;
+    const int G8 = G & ~7;
+    if (b >= G8) return b;
+    return (b & 7) * (G8 >> 3) + (b >> 3);
+}
+
+// ------------------------------------------------- per-axis equilibrium
+// F_n(u), n = -N..N: N-fold convolution of the D1Q3 equilibrium at v = u/N,
+// i.e. of the step probabilities of Eq. maineq04 with c = 1, theta = N/3:
+// p+- = 1/6 +- v/2 + v^2/2 and p0 = 1 - p+ - p-.
+template <int N, class T = float>
+__device__ __forceinline__ void axis_equilibrium(T u, T (&F)[2 * N + 1])
+{
+    if constexpr (N == 0) {
+        F[0] = T(1);
+    } else {
+        const T v = u / (T)N;
+        const T hv = T(0.5) * v;
+        const T pp = hv * (v + T(1)) + T(1) / T(6);
+        const T pm = hv * (v - T(1)) + T(1) / T(6);
+        const T p0 = (T(1) - pp) - pm;
+        F[0] = pm;
+        F[1] = p0;
+        F[2] = pp;
+        // multiply by (pm z^-1 + p0 + pp z) once per further level, in place
+        // from the top entry down (entry j reads entries j, j-1, j-2 of the
+        // previous level)
+        unroll<N - 1>([&](auto K) {
+            constexpr int k = K + 2;  // level being built; the previous has 2k-1 entries
+            unroll<2 * k + 1>([&](auto J) {
+                constexpr int j = 2 * k - (int)J;
+                T s = T(0);
+                if constexpr (j <= 2 * k - 2) s = pm * F[j];
+                if constexpr (j >= 1 && j - 1 <= 2 * k - 2) s = p0 * F[j - 1] + s;
+                if constexpr (j >= 2) s = pp * F[j - 2] + s;
+                F[j] = s;
+            });
+        });
+    }
+}
+
+// ------------------------------------------------------------ the pull
+// Working value of a population: f itself (plain storage) or its deviation
+// f - S_ab from the rest state (shifted storage).
+template <int LX, int LY, int ST>
+struct Lat {
+    static constexpr int QX = 2 * LX + 1, QY = 2 * LY + 1, Q = QX * QY;
+    static constexpr int EB = Elem<ST>::bytes;
+    static constexpr bool shifted = Elem<ST>::shifted;
+};
+
+// Mass absorbed by a diffuse wall in column x: the post-collision
+// populations that leave through the wall in this streaming and would land in
+// column x (sources at x - c_x in the rows within reach of the wall).  The
+// wall re-emits it into column x as rho_w(x) = A(x) / J+ times the
+// unit-density equilibrium at the wall speed over the populations pointing
+// into the fluid, which conserves the mass of every column.  `mom` receives
+// the x momentum of the absorbed populations when requested.
+template <int LX, int LY, int ST, bool BOTTOM>
+__device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, int x, float *mom)
+{
+    using L = Lat<LX, LY, ST>;
+    float s = 0.0f, m = 0.0f;
+    unroll<L::QY>([&](auto B) {
+        constexpr int b = B, cb = b - LY;
+        if constexpr ((BOTTOM && cb < 0) || (!BOTTOM && cb > 0)) {
+            constexpr int depth = cb < 0 ? -cb : cb;
+            unroll<depth>([&](auto R) {
+                const int row = BOTTOM ? (int)R : p.ny - 1 - (int)R;
+                const uint32_t base = (uint32_t)(row * p.nxp + x + kGhost - LX) * (uint32_t)L::EB;
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, ca = a - LX;
+                    const float v = ld<ST>(rs, base + (LX - ca) * L::EB, (uint32_t)(b * L::QX + a) * p.plane_bytes);
+                    s += v;
+                    if (mom) m = __builtin_fmaf((float)ca, v, m);
+                });
+            });
+        }
+    });
+    if (mom) *mom = m;  // the shift is even in c_x: it carries no x momentum
+    if constexpr (L::shifted) s += kShift<LX, LY>.absorbed;
+    return s;
+}
+
+// Pre-collision populations of node (x, y) at the new time: pulled from the
+// source buffer, or emitted by a wall where the source row is outside.
+template <int LX, int LY, int ST, int BCY>
+__device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, int x, int y, float (&v)[2 * LY + 1][2 * LX + 1])
+{
+    using L = Lat<LX, LY, ST>;
+    float rw[2] = {0.0f, 0.0f};
+    if constexpr (BCY == BCY_WALL) {
+        // the mass the FP32 emission tables give out per unit wall density
+        constexpr double jp = half_flux_f32<LY>();
+        if (y < LY) rw[0] = wall_absorbed<LX, LY, ST, true>(p, rs, x, nullptr) / (float)(jp * p.fwsum[0]);
+        if (y >= p.ny - LY) rw[1] = wall_absorbed<LX, LY, ST, false>(p, rs, x, nullptr) / (float)(jp * p.fwsum[1]);
+    }
+    unroll<L::QY>([&](auto B) {
+        constexpr int b = B, cb = b - LY;
+        int ys = y - cb;
+        bool emit = false;
+        if constexpr (BCY == BCY_WALL) {
+            if constexpr (cb > 0) emit = ys < 0;
+            if constexpr (cb < 0) emit = ys >= p.ny;
+        } else {
+            if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
+            if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
+        }
+        if (emit) {
+            constexpr int side = cb > 0 ? 0 : 1;
+            const float rwb = rw[side] * (float)kRest<LY>.w[b];
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A;
+                if constexpr (L::shifted)
+                    v[b][a] = __builtin_fmaf(rwb, p.fw[side][a], -kShift<LX, LY>.s[b][a]);
+                else
+                    v[b][a] = rwb * p.fw[side][a];
+            });
+        } else {
+            const uint32_t base = (uint32_t)(ys * p.nxp + x + kGhost - LX) * (uint32_t)L::EB;
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, ca = a - LX;
+                v[b][a] = ld<ST>(rs, base + (LX - ca) * L::EB, (uint32_t)(b * L::QX + a) * p.plane_bytes);
+            });
+        }
+    });
+}
+
+// Density, momentum and velocity from working values (the shift has unit
+// mass and no momentum).
+template <int LX, int LY, int ST>
+__device__ __forceinline__ void density_velocity(const float (&v)[2 * LY + 1][2 * LX + 1], float &rho, float &jx,
+                                                 float &jy, float &ux, float &uy)
+{
+    using L = Lat<LX, LY, ST>;
+    float r = 0.0f;
+    jx = 0.0f;
+    jy = 0.0f;
+    unroll<L::QY>([&](auto B) {
+        constexpr int b = B, cb = b - LY;
+        float rs = 0.0f, rx = 0.0f;
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, ca = a - LX;
+            rs += v[b][a];
+            if constexpr (ca != 0) rx = __builtin_fmaf((float)ca, v[b][a], rx);
+        });
+        r += rs;
+        jx += rx;
+        if constexpr (cb != 0) jy = __builtin_fmaf((float)cb, rs, jy);
+    });
+    rho = L::shifted ? 1.0f + r : r;
+    const float inv = 1.0f / rho;
+    ux = jx * inv;
+    uy = jy * inv;
+}
+
+// BGK collision with the linear force, in place on working values:
+// f* = f + omega (rho F_a(u_x) F_b(u_y) - f) + W_a W_b c_a g / theta_x.
+// The relaxation is written as f + omega (f^eq - f) so that no rounded
+// 1 - omega enters.  In exact arithmetic f^eq carries the mass and momentum
+// of f; the FP32 tables rho F_a and F_b do so only up to their rounding,
+// deterministically in u, which a channel flow (u constant along rows) would
+// integrate into a drift over thousands of steps.  The exact (FP64) sums of
+// the FP32 tables give that defect, and it is taken out of the equilibrium of
+// the rest population (mass) and of the +-1 populations (momentum).
+template <int LX, int LY, int ST>
+__device__ __forceinline__ void collide(const KArgs &p, float (&v)[2 * LY + 1][2 * LX + 1], float rho, float jx,
+                                        float jy, float ux, float uy)
+{
+    using L = Lat<LX, LY, ST>;
+    // per-axis equilibrium in FP64 (the FP64 FMA rate equals the unpacked FP32
+    // rate on this chip), each entry then rounded once to FP32
+    const float om = p.omega;
+    float rF[L::QX], gK[L::QX], Fy[L::QY];
+    double sx = 0.0, mx = 0.0, sy = 0.0, my = 0.0;
+    {
+        double Fd[L::QX];
+        axis_equilibrium<LX, double>((double)ux, Fd);
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, ca = a - LX;
+            rF[a] = (float)((double)rho * Fd[a]);
+            sx += (double)rF[a];
+            mx += (double)ca * (double)rF[a];
+            gK[a] = p.gth * (float)(kRest<LX>.w[a] * ca);
+        });
+    }
+    {
+        double Fd[L::QY];
+        axis_equilibrium<LY, double>((double)uy, Fd);
+        unroll<L::QY>([&](auto B) {
+            constexpr int b = B, cb = b - LY;
+            Fy[b] = (float)Fd[b];
+            sy += (double)Fy[b];
+            my += (double)cb * (double)Fy[b];
+        });
+    }
+    // sum f^eq = sx sy, sum f^eq c_x = mx sy, sum f^eq c_y = sx my (exactly, for
+    // the products of the FP32 tables)
+    const float dm = (float)(sx * sy - (double)rho);
+    const float hx = (float)(0.5 * (mx * sy - (double)jx));
+    const float hy = (float)(0.5 * (sx * my - (double)jy));
+    unroll<L::QY>([&](auto B) {
+        constexpr int b = B, cb = b - LY;
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, ca = a - LX;
+            float neq;  // f^eq - f
+            if constexpr (L::shifted)
+                neq = __builtin_fmaf(rF[a], Fy[b], -kShift<LX, LY>.s[b][a]) - v[b][a];
+            else
+                neq = __builtin_fmaf(rF[a], Fy[b], -v[b][a]);
+            if constexpr (ca == 0 && cb == 0) neq -= dm;
+            if constexpr (cb == 0 && ca == 1) neq -= hx;
+            if constexpr (cb == 0 && ca == -1) neq += hx;
+            if constexpr (ca == 0 && cb == 1) neq -= hy;
+            if constexpr (ca == 0 && cb == -1) neq += hy;
+            v[b][a] = __builtin_fmaf(gK[a], (float)kRest<LY>.w[b], __builtin_fmaf(om, neq, v[b][a]));
+        });
+    });
+}
+
+// Store working values at node x of row y, replicating edge nodes into the
+// ghost columns when x is periodic.  `h` seeds the stochastic rounding.
+template <int LX, int LY, int ST, int BCX>
+__device__ __forceinline__ void store_node(const KArgs &p, rsrc_t rd, int x, int y,
+                                           const float (&v)[2 * LY + 1][2 * LX + 1], uint32_t h)
+{
+    using L = Lat<LX, LY, ST>;
+    // columns holding node x: its own, and with periodic x every column of
+    // [G - LX, G + nx + LX) congruent to it modulo nx
+    int pc = x + kGhost;
+    if constexpr (BCX == BCX_PERIODIC) pc = kGhost - LX + (x + LX) % p.nx;
+    for (; pc < kGhost + p.nx + LX; pc += p.nx) {
+        const uint32_t off = (uint32_t)(y * p.nxp + pc) * (uint32_t)L::EB;
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B;
+                uint32_t r = 0;
+                if constexpr (ST == ST_BF16SR) r = rnd_of<b * L::QX + a>(h);
+                st<ST>(rd, off, (uint32_t)(b * L::QX + a) * p.plane_bytes, v[b][a], r);
+            });
+        });
+        if constexpr (BCX != BCX_PERIODIC) break;
+    }
+}
+
+// Hash of (node, step) for the stochastic rounding: reproducible, independent
+// of the launch shape.
+__device__ __forceinline__ uint32_t node_hash(const KArgs &p, int i)
+{
+    return mix32((uint32_t)i ^ p.seed);
+}
+
+// ------------------------------------------------------------- kernels
+// One time step: pull from f*(t-1), collide, write f*(t).
+template <int LX, int LY, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
+{
+    using L = Lat<LX, LY, ST>;
+    const int i = tile_index(p) * kBlock + (int)threadIdx.x;
+    if (i >= p.nodes) return;
+    const int y = i / p.nx, x = i - y * p.nx;
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
+    float v[L::QY][L::QX];
+    pull<LX, LY, ST, BCY>(p, rs, x, y, v);
+    float rho, jx, jy, ux, uy;
+    density_velocity<LX, LY, ST>(v, rho, jx, jy, ux, uy);
+    collide<LX, LY, ST>(p, v, rho, jx, jy, ux, uy);
+    store_node<LX, LY, ST, BCX>(p, rd, x, y, v, ST == ST_BF16SR ? node_hash(p, i) : 0u);
+}
+
+// Moments (and optionally the populations) of the pre-collision state f(t).
+// A diagnostics kernel: the stored FP32 values are summed in FP64, so the
+// reported moments carry the state's error and no evaluation noise.
+template <int LX, int LY, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void observe_kernel(KArgs p)
+{
+    using L = Lat<LX, LY, ST>;
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (i >= p.nodes) return;
+    const int y = i / p.nx, x = i - y * p.nx;
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    float v[L::QY][L::QX];
+    if (p.local) {
+        const uint32_t base = (uint32_t)(y * p.nxp + x + kGhost) * (uint32_t)L::EB;
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B;
+                v[b][a] = ld<ST>(rs, base, (uint32_t)(b * L::QX + a) * p.plane_bytes);
+            });
+        });
+    } else {
+        pull<LX, LY, ST, BCY>(p, rs, x, y, v);
+    }
+    double r = 0.0, jx = 0.0, jy = 0.0;
+    unroll<L::QY>([&](auto B) {
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, b = B, ca = a - LX, cb = b - LY;
+            const double f = v[b][a];
+            r += f;
+            jx += ca * f;
+            jy += cb * f;
+        });
+    });
+    const double rho = L::shifted ? 1.0 + r : r;
+    const double ux = jx / rho, uy = jy / rho;
+    // second moments from f - f^eq: the product equilibrium has
+    // sum f^eq c_x^2 = rho (u_x^2 + theta_x) and sum f^eq c_x c_y = rho u_x u_y,
+    // so T = (theta_x + theta_y + sum (f - f^eq) |c|^2 / rho) / dims and
+    // Pxy = sum (f - f^eq) c_x c_y
+    double Fx[L::QX], Fy[L::QY];
+    axis_equilibrium<LX, double>(ux, Fx);
+    axis_equilibrium<LY, double>(uy, Fy);
+    double e2 = 0.0, exy = 0.0;
+    unroll<L::QY>([&](auto B) {
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, b = B, ca = a - LX, cb = b - LY;
+            double f = v[b][a];
+            if constexpr (L::shifted) f += (double)kShift<LX, LY>.s[b][a];
+            const double dev = f - rho * Fx[a] * Fy[b];
+            e2 += (ca * ca + cb * cb) * dev;
+            exy += (ca * cb) * dev;
+        });
+    });
+    constexpr int dims = LY > 0 ? 2 : 1;
+    if (p.o_rho) p.o_rho[i] = (float)rho;
+    if (p.o_ux) p.o_ux[i] = (float)ux;
+    if (p.o_uy) p.o_uy[i] = (float)uy;
+    if (p.o_T) p.o_T[i] = (float)(((LX + LY) / 3.0 + e2 / rho) / dims);
+    if (p.o_pxy) p.o_pxy[i] = (float)exy;
+    if (p.o_f) {
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B;
+                float f = v[b][a];
+                if constexpr (L::shifted) f += kShift<LX, LY>.s[b][a];
+                p.o_f[(size_t)(b * L::QX + a) * p.nodes + i] = f;
+            });
+        });
+    }
+}
+
+// f(0) from fields (equilibrium) or given populations; writes f(0) into dst2
+// and f*(0) = collide(f(0)) into dst.
+template <int LX, int LY, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void init_kernel(KArgs p)
+{
+    using L = Lat<LX, LY, ST>;
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (i >= p.nodes) return;
+    const int y = i / p.nx, x = i - y * p.nx;
+    float v[L::QY][L::QX];
+    if (p.i_f) {
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B;
+                v[b][a] = p.i_f[(size_t)(b * L::QX + a) * p.nodes + i];
+            });
+        });
+    } else {
+        const float rho = p.i_rho ? p.i_rho[i] : 1.0f;
+        const float ux = p.i_ux ? p.i_ux[i] : 0.0f;
+        const float uy = (p.i_uy && LY > 0) ? p.i_uy[i] : 0.0f;
+        double Fx[L::QX], Fy[L::QY];
+        axis_equilibrium<LX, double>((double)ux, Fx);
+        axis_equilibrium<LY, double>((double)uy, Fy);
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B;
+                v[b][a] = (float)((double)rho * Fx[a] * Fy[b]);
+            });
+        });
+    }
+    if constexpr (L::shifted) {
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B;
+                v[b][a] -= kShift<LX, LY>.s[b][a];
+            });
+        });
+    }
+    const uint32_t h = ST == ST_BF16SR ? node_hash(p, i) : 0u;
+    if constexpr (Elem<ST>::bytes == 2) {
+        // round f(0) as the storage will, so that f*(0) is the collision of the
+        // stored f(0) (the stores below are then exact)
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B;
+                v[b][a] = quantize<ST>(v[b][a], rnd_of<b * L::QX + a>(h));
+            });
+        });
+    }
+    const rsrc_t r2 = make_rsrc(p.dst2, p.buf_bytes);
+    store_node<LX, LY, ST, BCX>(p, r2, x, y, v, h);
+    float rho, jx, jy, ux, uy;
+    density_velocity<LX, LY, ST>(v, rho, jx, jy, ux, uy);
+    collide<LX, LY, ST>(p, v, rho, jx, jy, ux, uy);
+    const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
+    store_node<LX, LY, ST, BCX>(p, rd, x, y, v, mix32(h));
+}
+
+// Ghost columns of the fixed equilibrium ends: f = rho_end W_a W_b (working
+// value minus the shift when shifted), in both buffers.  One thread per
+// (q, row, ghost column).
+template <int LX, int LY, int ST>
+__global__ __launch_bounds__(kBlock) void ends_kernel(KArgs p, float rho_left, float rho_right)
+{
+    using L = Lat<LX, LY, ST>;
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    const int per_row = 2 * LX;
+    if (i >= L::Q * p.ny * per_row) return;
+    const int q = i / (p.ny * per_row);
+    const int rem = i - q * p.ny * per_row;
+    const int y = rem / per_row, k = rem - y * per_row;
+    const bool left = k < LX;
+    // k in [0, LX): columns G-LX .. G-1; k in [LX, 2LX): columns G+nx .. G+nx+LX-1
+    const int pc = left ? kGhost - LX + k : kGhost + p.nx + (k - LX);
+    const int a = q % L::QX, b = q / L::QX;
+    double w = 1.0, s = 0.0;
+    // run-time index into compile-time tables
+    unroll<L::QY>([&](auto B) {
+        unroll<L::QX>([&](auto A) {
+            if (A == a && B == b) {
+                w = kRest<LX>.w[A] * kRest<LY>.w[B];
+                s = kShift<LX, LY>.s[B][A];
+            }
+        });
+    });
+    const double rho = left ? rho_left : rho_right;
+    const float val = (float)(L::shifted ? rho * w - s : rho * w);
+    const uint32_t off = (uint32_t)(y * p.nxp + pc) * (uint32_t)L::EB;
+    // the ends are fixed data, not dynamics: round them to nearest
+    constexpr int STN = Elem<ST>::bytes == 2 ? (int)ST_BF16S : ST;
+    st<STN>(make_rsrc(p.dst, p.buf_bytes), off, (uint32_t)q * p.plane_bytes, val);
+    st<STN>(make_rsrc(p.dst2, p.buf_bytes), off, (uint32_t)q * p.plane_bytes, val);
+}
+
+// Global FP64 sums (glbm_stats): per-block partials.
+// [0] mass  [1] momentum x  [2] momentum y  [3] energy (post)  [4] sum u_x^2
+// [5] sum (u_x(t) - u_x(t-1))^2  [6] bottom absorbed mass  [7] bottom x momentum
+// [8] top absorbed mass  [9] top x momentum  [10] non-positive nodes
+template <int LX, int LY, int ST, int BCY>
+__global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
+{
+    using L = Lat<LX, LY, ST>;
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    double acc[kNumStats];
+    for (int k = 0; k < kNumStats; ++k) acc[k] = 0.0;
+    if (i < p.nodes) {
+        const int y = i / p.nx, x = i - y * p.nx;
+        const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+        const uint32_t base = (uint32_t)(y * p.nxp + x + kGhost) * (uint32_t)L::EB;
+        double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B, ca = a - LX, cb = b - LY;
+                const double f = ld<ST>(rs, base, (uint32_t)(b * L::QX + a) * p.plane_bytes);
+                r += f;
+                jx += ca * f;
+                jy += cb * f;
+                e += (ca * ca + cb * cb) * f;
+            });
+        });
+        if constexpr (L::shifted) {
+            r += 1.0;
+            e += (double)kShift<LX, LY>.sxx + (double)kShift<LX, LY>.syy;
+        }
+        // f*(t) carries the force momentum g of step t's collision
+        const double jx_pre = jx - p.g;
+        const double ux = jx_pre / r, uy = jy / r;
+        acc[0] = r;
+        acc[1] = jx_pre;
+        acc[2] = jy;
+        acc[3] = e;
+        acc[4] = ux * ux;
+        if (p.prev) {
+            const rsrc_t rp = make_rsrc(p.prev, p.buf_bytes);
+            double r0 = 0.0, j0 = 0.0;
+            unroll<L::QY>([&](auto B) {
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, b = B, ca = a - LX;
+                    const double f = ld<ST>(rp, base, (uint32_t)(b * L::QX + a) * p.plane_bytes);
+                    r0 += f;
+                    j0 += ca * f;
+                });
+            });
+            if constexpr (L::shifted) r0 += 1.0;
+            const double d = ux - (j0 - p.g) / r0;
+            acc[5] = d * d;
+        }
+        // positivity domain of section 3: |u| <= sqrt(2 N theta) = N sqrt(2/3)
+        const double lim = 2.0 / 3.0;
+        if (ux * ux > lim * LX * LX || (LY > 0 && uy * uy > lim * LY * LY)) acc[10] = 1.0;
+        if constexpr (BCY == BCY_WALL) {
+            if (y == 0) {
+                float m;
+                const float A = wall_absorbed<LX, LY, ST, true>(p, rs, x, &m);
+                acc[6] = A;
+                acc[7] = (double)m - (double)A * p.uw[0];
+            }
+            if (y == p.ny - 1) {
+                float m;
+                const float A = wall_absorbed<LX, LY, ST, false>(p, rs, x, &m);
+                acc[8] = A;
+                acc[9] = (double)m - (double)A * p.uw[1];
+            }
+        }
+    }
+    // wave reduction, then across the block's waves through LDS
+    __shared__ double red[kBlock / 64][kNumStats];
+    for (int k = 0; k < kNumStats; ++k) {
+        double s = acc[k];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        acc[k] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < kNumStats; ++k) red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < kNumStats) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        p.partials[(size_t)blockIdx.x * kNumStats + threadIdx.x] = s;
+    }
+}
+
+}  // namespace glbm

@@ -1,0 +1,85 @@
+// Kernel instantiations for one hierarchy level, selected at compile time
+// with -DGLBM_LEVEL=N (N = 1..7); -DGLBM_LEVEL=0 builds the mixed-level
+// lattices.  Each level is its own object file so the build runs in parallel.
+#include "glbm_internal.h"
+
+namespace glbm {
+namespace {
+
+template <int LX, int LY, int ST, int BCX, int BCY>
+struct Launchers {
+    static hipError_t step(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t observe(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((observe_kernel<LX, LY, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t init(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((init_kernel<LX, LY, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t stats(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((stats_kernel<LX, LY, ST, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t ends(const KArgs &a, int grid, float rl, float rr, hipStream_t s)
+    {
+        hipLaunchKernelGGL((ends_kernel<LX, LY, ST>), dim3(grid), dim3(kBlock), 0, s, a, rl, rr);
+        return hipGetLastError();
+    }
+    static void add()
+    {
+        Variant *v = variant_slot(LX, LY, ST, BCX, BCY);
+        v->step = &step;
+        v->observe = &observe;
+        v->init = &init;
+        v->stats = &stats;
+        v->ends = BCX == BCX_EQ ? &ends : nullptr;
+    }
+};
+
+template <int LX, int LY, int BCX, int BCY>
+void add_all_storages()
+{
+    Launchers<LX, LY, ST_F32, BCX, BCY>::add();
+    Launchers<LX, LY, ST_F32S, BCX, BCY>::add();
+    Launchers<LX, LY, ST_BF16S, BCX, BCY>::add();
+    Launchers<LX, LY, ST_BF16SR, BCX, BCY>::add();
+}
+
+}  // namespace
+
+#if GLBM_LEVEL >= 1
+#define GLBM_CAT2(a, b) a##b
+#define GLBM_CAT(a, b) GLBM_CAT2(a, b)
+void GLBM_CAT(register_level_, GLBM_LEVEL)()
+{
+    constexpr int N = GLBM_LEVEL;
+    // one dimension: periodic or fixed equilibrium ends
+    add_all_storages<N, 0, BCX_PERIODIC, BCY_PERIODIC>();
+    add_all_storages<N, 0, BCX_EQ, BCY_PERIODIC>();
+    // two dimensions, same level on both axes: periodic or walls across y
+    add_all_storages<N, N, BCX_PERIODIC, BCY_PERIODIC>();
+    add_all_storages<N, N, BCX_PERIODIC, BCY_WALL>();
+}
+#else
+// Mixed lattices G-D1Q3 (streamwise x) x G-D1Q(2N+1) (across the walls), the
+// form the channel flows of sections 5.3-5.4 use.
+void register_mixed()
+{
+    add_all_storages<1, 2, BCX_PERIODIC, BCY_WALL>();
+    add_all_storages<1, 3, BCX_PERIODIC, BCY_WALL>();
+    add_all_storages<1, 4, BCX_PERIODIC, BCY_WALL>();
+    add_all_storages<1, 5, BCX_PERIODIC, BCY_WALL>();
+    add_all_storages<1, 6, BCX_PERIODIC, BCY_WALL>();
+    add_all_storages<1, 7, BCX_PERIODIC, BCY_WALL>();
+}
+#endif
+
+}  // namespace glbm

@@ -1,0 +1,257 @@
+"""ctypes binding of libglbm.so (the C-ABI declared in ``include/glbm.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  There is no
+fallback: if the library or a GPU is missing, :func:`load` and
+:class:`Solver` raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglbm.so")
+
+OK = 0
+BC = {"periodic": 0, "wall": 1, "eq_ends": 2}
+STORAGE = {"f32": 0, "f32_shifted": 1, "bf16_shifted": 2, "bf16_shifted_sr": 3}
+MAX_LEVEL = 7
+
+# Exported entry points of include/glbm.h (kept in sync by tests/test_abi.py).
+SYMBOLS = (
+    "glbm_population_bytes", "glbm_create", "glbm_init_fields", "glbm_init_populations",
+    "glbm_step", "glbm_moments", "glbm_get_populations", "glbm_stats", "glbm_info",
+    "glbm_destroy", "glbm_last_error",
+)
+
+
+class GlbmError(RuntimeError):
+    pass
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int32),
+        ("level_x", ctypes.c_int32),
+        ("level_y", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("nx", ctypes.c_int64),
+        ("ny", ctypes.c_int64),
+        ("tau", ctypes.c_double),
+        ("kn", ctypes.c_double),
+        ("bc_x", ctypes.c_int32),
+        ("bc_y", ctypes.c_int32),
+        ("wall_u", ctypes.c_double * 2),
+        ("end_rho", ctypes.c_double * 2),
+        ("g", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("time", ctypes.c_int64),
+        ("mass", ctypes.c_double),
+        ("momentum_x", ctypes.c_double),
+        ("momentum_y", ctypes.c_double),
+        ("energy_post", ctypes.c_double),
+        ("residual", ctypes.c_double),
+        ("wall_mass", ctypes.c_double * 2),
+        ("wall_momentum", ctypes.c_double * 2),
+        ("nonpositive_nodes", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libglbm.so (raises GlbmError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise GlbmError("libglbm.so not found at %s: run `python -m paper_1905_04597_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    vp, cp = ctypes.c_void_p, ctypes.POINTER(Config)
+    lib.glbm_population_bytes.argtypes = [cp]
+    lib.glbm_population_bytes.restype = ctypes.c_size_t
+    lib.glbm_create.argtypes = [cp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.glbm_create.restype = ctypes.c_int
+    lib.glbm_init_fields.argtypes = [vp, vp, vp, vp]
+    lib.glbm_init_populations.argtypes = [vp, vp]
+    lib.glbm_step.argtypes = [vp, ctypes.c_int64]
+    lib.glbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.glbm_get_populations.argtypes = [vp, vp]
+    lib.glbm_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.glbm_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.glbm_destroy.argtypes = [vp]
+    lib.glbm_last_error.argtypes = []
+    lib.glbm_last_error.restype = ctypes.c_char_p
+    for name in ("glbm_init_fields", "glbm_init_populations", "glbm_step", "glbm_moments",
+                 "glbm_get_populations", "glbm_stats", "glbm_info", "glbm_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        msg = load().glbm_last_error().decode(errors="replace")
+        raise GlbmError("%s failed (%d): %s" % (what, rc, msg))
+
+
+def make_config(dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0, bc_x="periodic", bc_y="periodic",
+                wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0, storage="f32") -> Config:
+    c = Config()
+    c.dims = int(dims)
+    c.level_x = int(level_x)
+    c.level_y = int(level_y)
+    c.storage = STORAGE[storage]
+    c.nx = int(nx)
+    c.ny = int(ny)
+    c.tau = float(tau)
+    c.kn = float(kn)
+    c.bc_x = BC[bc_x]
+    c.bc_y = BC[bc_y]
+    c.wall_u[0], c.wall_u[1] = float(wall_u[0]), float(wall_u[1])
+    c.end_rho[0], c.end_rho[1] = float(end_rho[0]), float(end_rho[1])
+    c.g = float(g)
+    return c
+
+
+def config_from_workload(w) -> Config:
+    return make_config(w.dims, w.level_x, w.level_y, w.nx, w.ny, w.tau, w.kn, w.bc_x, w.bc_y,
+                       w.wall_u, w.end_rho, w.g, w.storage)
+
+
+def population_bytes(cfg: Config) -> int:
+    n = load().glbm_population_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise GlbmError("invalid configuration: " + load().glbm_last_error().decode(errors="replace"))
+    return int(n)
+
+
+class Solver:
+    """One lattice on one GPU.
+
+    Buffers are two PyTorch uint8 tensors owned by this object; all work is
+    enqueued on ``stream`` (default: the current torch stream of ``device``).
+    """
+
+    def __init__(self, cfg: Config, device=None, stream=None, buffers=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise GlbmError("no GPU available: the glbm library has no CPU path")
+        self._torch = torch
+        self.lib = load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.cfg = cfg
+        self.nbytes = population_bytes(cfg)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            if buffers is None:
+                buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+            self.buffers = buffers
+            h = ctypes.c_void_p()
+            _check(self.lib.glbm_create(ctypes.byref(cfg), buffers[0].data_ptr(), buffers[1].data_ptr(),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "glbm_create")
+        self._h = h
+        self.dims = cfg.dims
+        self.nx = int(cfg.nx)
+        self.ny = int(cfg.ny) if cfg.dims == 2 else 1
+        self.level_x = int(cfg.level_x)
+        self.level_y = int(cfg.level_y) if cfg.dims == 2 else 0
+        self.Q = (2 * self.level_x + 1) * (2 * self.level_y + 1)
+        self._keep = []
+
+    # ------------------------------------------------------------- helpers
+    def _dev(self, a, shape):
+        torch = self._torch
+        if a is None:
+            return None
+        t = torch.as_tensor(a, dtype=torch.float32).to(self.device).contiguous()
+        if t.numel() != int(torch.tensor(shape).prod()):
+            raise GlbmError("expected %s values, got %d" % (shape, t.numel()))
+        return t
+
+    @staticmethod
+    def _ptr(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    # ---------------------------------------------------------------- API
+    def init_fields(self, rho=None, ux=None, uy=None):
+        shp = (self.ny, self.nx)
+        r, a, b = self._dev(rho, shp), self._dev(ux, shp), self._dev(uy, shp)
+        with self._torch.cuda.device(self.device):
+            _check(self.lib.glbm_init_fields(self._h, self._ptr(r), self._ptr(a), self._ptr(b)), "glbm_init_fields")
+        self._keep = [r, a, b]
+
+    def init_populations(self, f0):
+        t = self._dev(f0, (self.Q, self.ny, self.nx))
+        with self._torch.cuda.device(self.device):
+            _check(self.lib.glbm_init_populations(self._h, self._ptr(t)), "glbm_init_populations")
+        self._keep = [t]
+
+    def step(self, n: int = 1):
+        with self._torch.cuda.device(self.device):
+            _check(self.lib.glbm_step(self._h, int(n)), "glbm_step")
+
+    def moments(self, which=("rho", "ux", "uy", "T", "pxy")) -> dict:
+        torch = self._torch
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) for k in which}
+        ptrs = [self._ptr(out.get(k)) for k in ("rho", "ux", "uy", "T", "pxy")]
+        with torch.cuda.device(self.device):
+            _check(self.lib.glbm_moments(self._h, *ptrs), "glbm_moments")
+        return out
+
+    def populations(self):
+        torch = self._torch
+        out = torch.empty((self.Q, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self.lib.glbm_get_populations(self._h, self._ptr(out)), "glbm_get_populations")
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        with self._torch.cuda.device(self.device):
+            _check(self.lib.glbm_stats(self._h, ctypes.byref(s)), "glbm_stats")
+        return {
+            "time": s.time, "mass": s.mass, "momentum_x": s.momentum_x, "momentum_y": s.momentum_y,
+            "energy_post": s.energy_post, "residual": s.residual,
+            "wall_mass_bottom": s.wall_mass[0], "wall_mass_top": s.wall_mass[1],
+            "wall_momentum_bottom": s.wall_momentum[0], "wall_momentum_top": s.wall_momentum[1],
+            "nonpositive_nodes": s.nonpositive_nodes,
+        }
+
+    def info(self) -> dict:
+        tau, om = ctypes.c_double(), ctypes.c_double()
+        q, t = ctypes.c_int32(), ctypes.c_int64()
+        _check(self.lib.glbm_info(self._h, ctypes.byref(tau), ctypes.byref(om), ctypes.byref(q), ctypes.byref(t)),
+               "glbm_info")
+        return {"tau": tau.value, "omega": om.value, "nvel": q.value, "time": t.value}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.glbm_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def solver_for(workload, device=None, stream=None) -> Solver:
+    return Solver(config_from_workload(workload), device=device, stream=stream)

@@ -97,6 +97,21 @@ def random_fields(seed: int, nx: int, ny: int, rho_amp: float = 0.05, u_amp: flo
     return rho, ux, uy
 
 
+def wave_fields(nx: int, ny: int, rho_amp: float = 0.01, u_amp: float = 0.05, dims: int = 2):
+    """Smooth periodic fields (float32): one sine period of density and shear
+    across y, and of the y velocity along x."""
+    y = (np.arange(ny) + 0.5) / ny
+    x = (np.arange(nx) + 0.5) / nx
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    rho = (1.0 + rho_amp * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)).astype(np.float32)
+    ux = (u_amp * np.sin(2 * np.pi * Y)).astype(np.float32)
+    uy = (0.5 * u_amp * np.cos(2 * np.pi * X)).astype(np.float32)
+    if dims == 1:
+        ux = (u_amp * np.sin(2 * np.pi * X)).astype(np.float32)
+        uy[:] = 0
+    return rho, ux, uy
+
+
 def random_populations(seed: int, nvel: int, nx: int, ny: int, spread: float = 0.5) -> np.ndarray:
     """Positive random populations [q][y][x] (float32), each in (1 +- spread)/nvel."""
     rng = np.random.default_rng(seed)

@@ -1,0 +1,93 @@
+"""Helpers shared by the GPU tests: run the HIP library and the oracle on the
+same seeded inputs and compare them."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_1905_04597_amd import glbm
+from paper_1905_04597_amd import workloads as wl
+
+ORACLE_BC = {"periodic": oracle.BC_PERIODIC, "wall": oracle.BC_WALL, "eq_ends": oracle.BC_EQ_ENDS}
+# tolerance of the normwise relative error max|q - q_ref| / max|q_ref| per storage
+TOL = {"f32": 1e-5, "f32_shifted": 1e-5, "bf16_shifted": 1e-3, "bf16_shifted_sr": 1e-3}
+# Floors of the error scale for fields whose reference vanishes (u = 0 at
+# rest, u_y in a channel, Pxy of an equilibrium): velocities are measured
+# against at least 1e-2 (lattice units, ~1e-2 c_s) and the shear moment
+# against at least 1e-2 of the pressure scale theta.  FP32 storage alone
+# represents sum f c to ~1e-8 and sum f c_x c_y to ~6e-8 theta.
+U_FLOOR = 1e-2
+P_FLOOR_REL = 1e-2
+
+
+def rel_err(got, ref) -> float:
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = float(np.max(np.abs(ref)))
+    return float(np.max(np.abs(got - ref))) / scale if scale > 0 else float(np.max(np.abs(got)))
+
+
+def make_pair(params: dict, storage: str):
+    """Oracle and GPU solvers for the same configuration."""
+    p = dict(params)
+    dims = p["dims"]
+    orc = oracle.OracleSolver(dims, p["level_x"], p.get("level_y", 0), p["nx"], p.get("ny", 1),
+                              tau=p.get("tau", 0.0), kn=p.get("kn", 0.0),
+                              bc_x=ORACLE_BC[p.get("bc_x", "periodic")], bc_y=ORACLE_BC[p.get("bc_y", "periodic")],
+                              wall_u=p.get("wall_u", (0, 0)), end_rho=p.get("end_rho", (1, 1)), g=p.get("g", 0.0))
+    cfg = glbm.make_config(dims, p["level_x"], p.get("level_y", 0), p["nx"], p.get("ny", 1), p.get("tau", 0.0),
+                           p.get("kn", 0.0), p.get("bc_x", "periodic"), p.get("bc_y", "periodic"),
+                           p.get("wall_u", (0, 0)), p.get("end_rho", (1, 1)), p.get("g", 0.0), storage)
+    gpu = glbm.Solver(cfg)
+    return orc, gpu
+
+
+def initialise(orc, gpu, init: str, seed: int = 7):
+    ny, nx, Q = orc.ny, orc.nx, orc.Q
+    if init == "rest":
+        orc.init_fields()
+        gpu.init_fields()
+    elif init == "fields":
+        rho, ux, uy = wl.random_fields(seed, nx, ny, rho_amp=0.05, u_amp=0.1, dims=orc.dims)
+        orc.init_fields(rho.astype(np.float64), ux.astype(np.float64), uy.astype(np.float64))
+        gpu.init_fields(rho, ux, uy if orc.dims == 2 else None)
+    elif init == "wave":
+        rho, ux, uy = wl.wave_fields(nx, ny, dims=orc.dims)
+        orc.init_fields(rho.astype(np.float64), ux.astype(np.float64), uy.astype(np.float64))
+        gpu.init_fields(rho, ux, uy if orc.dims == 2 else None)
+    elif init == "populations":
+        f0 = wl.random_populations(seed, Q, nx, ny)
+        orc.init_populations(f0.astype(np.float64))
+        gpu.init_populations(f0)
+    elif init.startswith("sod"):
+        rho = wl.sod_density(nx, 1.0, 0.125)
+        orc.init_fields(rho.astype(np.float64))
+        gpu.init_fields(rho)
+    else:
+        raise ValueError(init)
+
+
+def gpu_moments(gpu) -> dict:
+    import torch
+
+    m = gpu.moments()
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in m.items()}
+
+
+def compare_moments(ref: dict, got: dict, theta: float = 1.0) -> dict:
+    """Normwise relative error max|q - q_ref| / max|q_ref| of each moment, with
+    the floors above for the velocity and shear scales."""
+    errs = {}
+    uscale = max(float(np.max(np.abs(ref["ux"]))), float(np.max(np.abs(ref["uy"]))), U_FLOOR)
+    floors = {"rho": 0.0, "ux": uscale, "uy": uscale, "T": 0.0, "pxy": P_FLOOR_REL * theta}
+    for k in ("rho", "ux", "uy", "T", "pxy"):
+        r, g = np.asarray(ref[k], dtype=np.float64), np.asarray(got[k], dtype=np.float64)
+        assert r.shape == g.shape, (k, r.shape, g.shape)
+        scale = max(float(np.max(np.abs(r))), floors[k])
+        errs[k] = float(np.max(np.abs(g - r))) / scale
+    return errs
+
+
+def fmt(errs: dict) -> str:
+    return "{" + ", ".join("%s: %.2e" % (k, v) for k, v in errs.items()) + "}"

@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every entry point include/glbm.h declares.
+
+Host-side checks only (configuration validation and sizing): no kernel is
+launched, so these run without a GPU.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1905_04597_amd import glbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "glbm.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(glbm.LIB_PATH), reason="libglbm.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(glbm_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_binding_symbols():
+    assert declared_functions() == sorted(glbm.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", glbm.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\bT (glbm_\w+)", out.stdout))
+    missing = [s for s in declared_functions() if s not in exported]
+    assert not missing, missing
+    lib = glbm.load()
+    for s in declared_functions():
+        assert hasattr(lib, s)
+
+
+def test_population_bytes_layout():
+    # [q][y][nxp], nxp = 64 + nx + N rounded up to a multiple of 64 columns,
+    # times the element size of the storage, rounded to 256 bytes
+    def nxp(nx, N):
+        return (64 + nx + N + 63) // 64 * 64
+    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="f32")
+    assert glbm.population_bytes(c) == ((121 * 1024 * nxp(4096, 5) * 4 + 255) // 256) * 256
+    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="bf16_shifted")
+    assert glbm.population_bytes(c) == ((121 * 1024 * nxp(4096, 5) * 2 + 255) // 256) * 256
+    c = glbm.make_config(1, 3, 0, 2000, 1, kn=0.01, bc_x="eq_ends")
+    assert glbm.population_bytes(c) == ((7 * nxp(2000, 3) * 4 + 255) // 256) * 256
+
+
+@pytest.mark.parametrize("kwargs,needle", [
+    (dict(dims=3, level_x=1), "dims"),
+    (dict(dims=1, level_x=0, nx=10), "level_x"),
+    (dict(dims=1, level_x=8, nx=10), "level_x"),
+    (dict(dims=2, level_x=3, level_y=3, nx=4, ny=5, bc_y="wall"), "2*level_y"),
+    (dict(dims=2, level_x=2, level_y=2, nx=4, ny=8, bc_x="eq_ends", bc_y="wall"), "combined"),
+    (dict(dims=2, level_x=7, level_y=7, nx=8192, ny=4096, bc_y="wall"), "4 GiB"),
+])
+def test_invalid_configs_are_rejected(kwargs, needle):
+    c = glbm.make_config(**kwargs)
+    assert glbm.load().glbm_population_bytes(ctypes.byref(c)) == 0
+    assert needle in glbm.load().glbm_last_error().decode()
+
+
+def test_create_rejects_missing_buffers_without_touching_the_gpu():
+    lib = glbm.load()
+    c = glbm.make_config(1, 2, 0, 16, 1, tau=0.7)
+    h = ctypes.c_void_p()
+    assert lib.glbm_create(ctypes.byref(c), None, None, None, ctypes.byref(h)) == -1
+    assert "buffers" in lib.glbm_last_error().decode()
+    assert lib.glbm_step(None, 1) == -1
