@@ -1,0 +1,124 @@
+"""Summaries of rocprofv3 output for the step kernel (kernel trace and memory
+counters), written as short text under ``profiles/``.
+
+    python -m paper_1905_04597_amd.profiling --workload NAME --storage S \\
+        --trace DIR/kt_results.db --fetch DIR/pmc_results.db --write DIR/pmc_results.db \\
+        --command "the rocprofv3 command lines" [--copy-bytes 2147483648]
+
+The memory counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled
+by what they read for a plain device copy of known size in the same run
+(bench.py copies 2 GiB before timing), giving HBM bytes per launch of the
+step kernel; the result is recorded, with a hash of the kernel sources, in
+``profiles/traffic_<workload>.json`` for bench.py to report.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sqlite3
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROFILES = os.path.join(ROOT, "profiles")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("glbm_device.h", "glbm_inst.hip", "glbm_api.hip"):
+        with open(os.path.join(ROOT, "paper_1905_04597_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_stats(db_path: str):
+    db = sqlite3.connect(db_path)
+    rows = list(db.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    # top_kernels reports microseconds
+    return [dict(name=r[0], calls=int(r[1]), total_us=float(r[2]), avg_us=float(r[3]), pct=float(r[4]))
+            for r in rows]
+
+
+def counter(db_path: str, name: str):
+    """Median value (KiB) per kernel name and grid size."""
+    db = sqlite3.connect(db_path)
+    by = {}
+    for k, v, g in db.execute("select kernel_name, value, grid_size from counters_collection where counter_name=?",
+                              (name,)):
+        by.setdefault((k, int(g)), []).append(float(v))
+    return {key: statistics.median(vs) for key, vs in by.items()}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--storage", required=True)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--copy-bytes", type=int, default=2 << 30)
+    ap.add_argument("--algorithmic-bytes", type=float, required=True)
+    a = ap.parse_args(argv)
+
+    stats = kernel_stats(a.trace)
+    fetch = counter(a.fetch, "FETCH_SIZE")
+    write = counter(a.write, "WRITE_SIZE")
+    copy_key = max((k for k in fetch if k[0] == COPY_KERNEL), key=lambda k: fetch[k])
+    f_scale = a.copy_bytes / (fetch[copy_key] * 1024.0)
+    w_scale = a.copy_bytes / (write[copy_key] * 1024.0)
+    step_key = [k for k in fetch if "step_kernel" in k[0]][0]
+    step_stat = [s for s in stats if "step_kernel" in s["name"]][0]
+    fb = fetch[step_key] * 1024.0 * f_scale
+    wb = write[step_key] * 1024.0 * w_scale
+    rec = {
+        "kernel": step_key[0], "grid": step_key[1], "avg_duration_us": step_stat["avg_us"],
+        "fetch_kib_raw": fetch[step_key], "write_kib_raw": write[step_key],
+        "fetch_scale": f_scale, "write_scale": w_scale,
+        "hbm_fetch_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb,
+        "hbm_bytes_per_launch": fb + wb, "algorithmic_bytes_per_launch": a.algorithmic_bytes,
+        "traffic_over_algorithmic": (fb + wb) / a.algorithmic_bytes,
+        "hbm_GBs": (fb + wb) / (step_stat["avg_us"] * 1e-6) / 1e9,
+    }
+    os.makedirs(PROFILES, exist_ok=True)
+    tpath = os.path.join(PROFILES, "traffic_%s.json" % a.workload)
+    allrec = {}
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            allrec = json.load(fh)
+    if allrec.get("kernel_source_hash") != kernel_source_hash():
+        allrec = {}
+    allrec["kernel_source_hash"] = kernel_source_hash()
+    allrec[a.storage] = rec
+    with open(tpath, "w") as fh:
+        json.dump(allrec, fh, indent=1)
+
+    md = os.path.join(PROFILES, "step_kernel_%s_%s.md" % (a.workload, a.storage))
+    with open(md, "w") as fh:
+        fh.write("# Step kernel, %s, storage %s\n\n" % (a.workload, a.storage))
+        fh.write("Commands (run on one MI355X):\n\n```\n%s\n```\n\n" % a.command.strip())
+        fh.write("## rocprofv3 --kernel-trace --stats\n\n| kernel | calls | avg us | total us | % |\n|---|---|---|---|---|\n")
+        for s in stats[:8]:
+            fh.write("| `%s` | %d | %.1f | %.1f | %.2f |\n" % (s["name"][:70], s["calls"], s["avg_us"], s["total_us"], s["pct"]))
+        fh.write("\n## Memory counters (median KiB per dispatch)\n\n| kernel | grid | FETCH_SIZE | WRITE_SIZE |\n|---|---|---|---|\n")
+        for k in sorted(set(fetch) | set(write), key=lambda k: -fetch.get(k, 0)):
+            if fetch.get(k, 0) + write.get(k, 0) < 1024:
+                continue
+            fh.write("| `%s` | %d | %.1f | %.1f |\n" % (k[0][:60], k[1], fetch.get(k, float("nan")), write.get(k, float("nan"))))
+        fh.write("\nCalibration: the %d-byte device copy (`%s`) reads FETCH_SIZE x %.3f and WRITE_SIZE x %.3f "
+                 "of its true bytes.\n\n" % (a.copy_bytes, COPY_KERNEL, 1 / f_scale, 1 / w_scale))
+        fh.write("## Step kernel per launch\n\n")
+        fh.write("- average duration: %.1f us\n" % rec["avg_duration_us"])
+        fh.write("- HBM bytes (scaled counters): fetch %.4g, write %.4g, total %.4g\n" % (fb, wb, fb + wb))
+        fh.write("- algorithmic bytes 2 Q s per node: %.4g (traffic / algorithmic = %.3f)\n"
+                 % (a.algorithmic_bytes, rec["traffic_over_algorithmic"]))
+        fh.write("- HBM rate from the counters: %.0f GB/s\n" % rec["hbm_GBs"])
+        fh.write("- kernel source hash: %s\n" % kernel_source_hash())
+    print(md)
+    print(tpath)
+
+
+if __name__ == "__main__":
+    main()
