@@ -163,6 +163,11 @@ struct Elem<ST_BF16SR> {
 };
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// Cache policy of the population stores: non-temporal (each value is written
+// once per step and read by other waves only in the next launch).  The loads
+// keep the default policy: neighbouring tiles re-read the halo lines from L2.
+constexpr int kStoreNT = 2;
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes)
@@ -189,15 +194,15 @@ __device__ __forceinline__ void st(rsrc_t r, uint32_t voff, uint32_t soff, float
 {
     if constexpr (ST == ST_BF16S) {
         const __bf16 h = (__bf16)v;  // round to nearest even (v_cvt_pk_bf16_f32)
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, kStoreNT);
     } else if constexpr (ST == ST_BF16SR) {
         // stochastic rounding in hardware (v_cvt_sr_bf16_f32): unbiased, so
         // increments far below one bf16 ulp still accumulate on average
         bf16x2_t h = {};
         h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)__builtin_bit_cast(uint32_t, h), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)__builtin_bit_cast(uint32_t, h), r, voff, soff, kStoreNT);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, kStoreNT);
     }
 }
 
@@ -400,11 +405,51 @@ __device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, int x, int y, fl
     });
 }
 
+// Populations of one node in registers, one FP32 value each.
+template <int LX, int LY>
+struct FloatRegs {
+    float (&v)[2 * LY + 1][2 * LX + 1];
+    template <int b, int a>
+    __device__ __forceinline__ float get() const { return v[b][a]; }
+    template <int b, int a>
+    __device__ __forceinline__ void put(float x) { v[b][a] = x; }
+};
+
+// Populations of one node in registers as BF16 pairs (two per 32-bit
+// register, population q in half q % 2 of register q / 2): half the register
+// footprint of FloatRegs, so twice the waves per SIMD.  put() rounds as the
+// storage does, so the stores are exact.
+template <int LX, int LY, int ST>
+struct PackedRegs {
+    static constexpr int QX = 2 * LX + 1, Q = QX * (2 * LY + 1), NP = (Q + 1) / 2;
+    uint32_t (&pk)[NP];
+    uint32_t h;  // node hash for the stochastic rounding
+    template <int b, int a>
+    __device__ __forceinline__ float get() const
+    {
+        constexpr int q = b * QX + a;
+        const uint32_t w = pk[q >> 1];
+        return __builtin_bit_cast(float, (q & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+    template <int b, int a>
+    __device__ __forceinline__ void put(float x)
+    {
+        constexpr int q = b * QX + a;
+        if constexpr (ST == ST_BF16SR) {
+            bf16x2_t hv = __builtin_bit_cast(bf16x2_t, pk[q >> 1]);
+            hv = __builtin_amdgcn_cvt_sr_bf16_f32(hv, x, rnd_of<q>(h), (q & 1) != 0);
+            pk[q >> 1] = __builtin_bit_cast(uint32_t, hv);
+        } else {
+            const uint32_t bits = __builtin_bit_cast(unsigned short, (__bf16)x);
+            pk[q >> 1] = (q & 1) ? ((pk[q >> 1] & 0xffffu) | (bits << 16)) : ((pk[q >> 1] & 0xffff0000u) | bits);
+        }
+    }
+};
+
 // Density, momentum and velocity from working values (the shift has unit
 // mass and no momentum).
-template <int LX, int LY, int ST>
-__device__ __forceinline__ void density_velocity(const float (&v)[2 * LY + 1][2 * LX + 1], float &rho, float &jx,
-                                                 float &jy, float &ux, float &uy)
+template <int LX, int LY, int ST, class Regs>
+__device__ __forceinline__ void density_velocity(const Regs &v, float &rho, float &jx, float &jy, float &ux, float &uy)
 {
     using L = Lat<LX, LY, ST>;
     float r = 0.0f;
@@ -415,8 +460,9 @@ __device__ __forceinline__ void density_velocity(const float (&v)[2 * LY + 1][2 
         float rs = 0.0f, rx = 0.0f;
         unroll<L::QX>([&](auto A) {
             constexpr int a = A, ca = a - LX;
-            rs += v[b][a];
-            if constexpr (ca != 0) rx = __builtin_fmaf((float)ca, v[b][a], rx);
+            const float f = v.template get<b, a>();
+            rs += f;
+            if constexpr (ca != 0) rx = __builtin_fmaf((float)ca, f, rx);
         });
         r += rs;
         jx += rx;
@@ -437,9 +483,8 @@ __device__ __forceinline__ void density_velocity(const float (&v)[2 * LY + 1][2 
 // integrate into a drift over thousands of steps.  The exact (FP64) sums of
 // the FP32 tables give that defect, and it is taken out of the equilibrium of
 // the rest population (mass) and of the +-1 populations (momentum).
-template <int LX, int LY, int ST>
-__device__ __forceinline__ void collide(const KArgs &p, float (&v)[2 * LY + 1][2 * LX + 1], float rho, float jx,
-                                        float jy, float ux, float uy)
+template <int LX, int LY, int ST, class Regs>
+__device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, float jx, float jy, float ux, float uy)
 {
     using L = Lat<LX, LY, ST>;
     // per-axis equilibrium in FP64 (the FP64 FMA rate equals the unpacked FP32
@@ -477,17 +522,18 @@ __device__ __forceinline__ void collide(const KArgs &p, float (&v)[2 * LY + 1][2
         constexpr int b = B, cb = b - LY;
         unroll<L::QX>([&](auto A) {
             constexpr int a = A, ca = a - LX;
+            const float f = v.template get<b, a>();
             float neq;  // f^eq - f
             if constexpr (L::shifted)
-                neq = __builtin_fmaf(rF[a], Fy[b], -kShift<LX, LY>.s[b][a]) - v[b][a];
+                neq = __builtin_fmaf(rF[a], Fy[b], -kShift<LX, LY>.s[b][a]) - f;
             else
-                neq = __builtin_fmaf(rF[a], Fy[b], -v[b][a]);
+                neq = __builtin_fmaf(rF[a], Fy[b], -f);
             if constexpr (ca == 0 && cb == 0) neq -= dm;
             if constexpr (cb == 0 && ca == 1) neq -= hx;
             if constexpr (cb == 0 && ca == -1) neq += hx;
             if constexpr (ca == 0 && cb == 1) neq -= hy;
             if constexpr (ca == 0 && cb == -1) neq += hy;
-            v[b][a] = __builtin_fmaf(gK[a], (float)kRest<LY>.w[b], __builtin_fmaf(om, neq, v[b][a]));
+            v.template put<b, a>(__builtin_fmaf(gK[a], (float)kRest<LY>.w[b], __builtin_fmaf(om, neq, f)));
         });
     });
 }
@@ -525,22 +571,89 @@ __device__ __forceinline__ uint32_t node_hash(const KArgs &p, int i)
 }
 
 // ------------------------------------------------------------- kernels
-// One time step: pull from f*(t-1), collide, write f*(t).
+// One step of a node with 16-bit storage that takes no wall emission: the
+// populations stay packed two per register from the loads to the stores.
 template <int LX, int LY, int ST, int BCX, int BCY>
+__device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd, int x, int y, uint32_t h)
+{
+    using L = Lat<LX, LY, ST>;
+    using P = PackedRegs<LX, LY, ST>;
+    uint32_t pk[P::NP];
+    unroll<L::QY>([&](auto B) {
+        constexpr int b = B, cb = b - LY;
+        int ys = y - cb;
+        if constexpr (BCY != BCY_WALL) {
+            if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
+            if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
+        }
+        const uint32_t base = (uint32_t)(ys * p.nxp + x + kGhost - LX) * 2u;
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, ca = a - LX, q = b * L::QX + a;
+            const uint32_t raw = (uint32_t)__builtin_bit_cast(
+                unsigned short, __builtin_amdgcn_raw_buffer_load_b16(rs, base + (LX - ca) * 2, (uint32_t)q * p.plane_bytes, 0));
+            if constexpr ((q & 1) == 0)
+                pk[q >> 1] = raw;
+            else
+                pk[q >> 1] |= raw << 16;
+        });
+    });
+    P regs{pk, h};
+    float rho, jx, jy, ux, uy;
+    density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
+    collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
+    int pc = x + kGhost;
+    if constexpr (BCX == BCX_PERIODIC) pc = kGhost - LX + (x + LX) % p.nx;
+    for (; pc < kGhost + p.nx + LX; pc += p.nx) {
+        const uint32_t off = (uint32_t)(y * p.nxp + pc) * 2u;
+        unroll<L::Q>([&](auto Qi) {
+            constexpr int q = Qi;
+            const unsigned short half = (q & 1) ? (unsigned short)(pk[q >> 1] >> 16) : (unsigned short)pk[q >> 1];
+            __builtin_amdgcn_raw_buffer_store_b16(half, rd, off, (uint32_t)q * p.plane_bytes, kStoreNT);
+        });
+        if constexpr (BCX != BCX_PERIODIC) break;
+    }
+}
+
+// Rows a step launch covers: all of them, the rows that take no wall
+// emission, or the LY rows next to each wall.
+enum StepRows { ROWS_ALL = 0, ROWS_INTERIOR = 1, ROWS_WALLS = 2 };
+
+// One time step: pull from f*(t-1), collide, write f*(t).  With 16-bit
+// storage the populations stay packed in registers (PackedRegs) wherever no
+// wall emission enters; the wall rows of such a lattice are a separate launch
+// (ROWS_WALLS, FP32 registers, so that emitted populations enter the collision
+// unrounded), which keeps the packed kernel's register allocation its own.
+template <int LX, int LY, int ST, int BCX, int BCY, int ROWS>
 __global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
 {
     using L = Lat<LX, LY, ST>;
-    const int i = tile_index(p) * kBlock + (int)threadIdx.x;
-    if (i >= p.nodes) return;
-    const int y = i / p.nx, x = i - y * p.nx;
+    int i = tile_index(p) * kBlock + (int)threadIdx.x;
+    int y, x;
+    if constexpr (ROWS == ROWS_ALL) {
+        if (i >= p.nodes) return;
+    } else if constexpr (ROWS == ROWS_INTERIOR) {
+        if (i >= (p.ny - 2 * LY) * p.nx) return;
+        i += LY * p.nx;
+    } else {
+        if (i >= 2 * LY * p.nx) return;
+        if (i >= LY * p.nx) i += (p.ny - 2 * LY) * p.nx;
+    }
+    y = i / p.nx;
+    x = i - y * p.nx;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
-    float v[L::QY][L::QX];
-    pull<LX, LY, ST, BCY>(p, rs, x, y, v);
-    float rho, jx, jy, ux, uy;
-    density_velocity<LX, LY, ST>(v, rho, jx, jy, ux, uy);
-    collide<LX, LY, ST>(p, v, rho, jx, jy, ux, uy);
-    store_node<LX, LY, ST, BCX>(p, rd, x, y, v, ST == ST_BF16SR ? node_hash(p, i) : 0u);
+    const uint32_t h = ST == ST_BF16SR ? node_hash(p, i) : 0u;
+    if constexpr (L::EB == 2 && ROWS != ROWS_WALLS) {
+        step_packed<LX, LY, ST, BCX, BCY>(p, rs, rd, x, y, h);
+    } else {
+        float v[L::QY][L::QX];
+        pull<LX, LY, ST, BCY>(p, rs, x, y, v);
+        FloatRegs<LX, LY> regs{v};
+        float rho, jx, jy, ux, uy;
+        density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
+        collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
+        store_node<LX, LY, ST, BCX>(p, rd, x, y, v, h);
+    }
 }
 
 // Moments (and optionally the populations) of the pre-collision state f(t).
@@ -666,9 +779,10 @@ __global__ __launch_bounds__(kBlock) void init_kernel(KArgs p)
     }
     const rsrc_t r2 = make_rsrc(p.dst2, p.buf_bytes);
     store_node<LX, LY, ST, BCX>(p, r2, x, y, v, h);
+    FloatRegs<LX, LY> regs{v};
     float rho, jx, jy, ux, uy;
-    density_velocity<LX, LY, ST>(v, rho, jx, jy, ux, uy);
-    collide<LX, LY, ST>(p, v, rho, jx, jy, ux, uy);
+    density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
+    collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
     store_node<LX, LY, ST, BCX>(p, rd, x, y, v, mix32(h));
 }

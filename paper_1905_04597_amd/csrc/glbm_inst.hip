@@ -10,7 +10,17 @@ template <int LX, int LY, int ST, int BCX, int BCY>
 struct Launchers {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
-        hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        if constexpr (Elem<ST>::bytes == 2 && BCY == BCY_WALL) {
+            // packed interior rows, then the rows next to the walls
+            const int interior = (a.ny - 2 * LY) * a.nx, walls = 2 * LY * a.nx;
+            if (interior > 0)
+                hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>),
+                                   dim3((interior + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>), dim3((walls + kBlock - 1) / kBlock),
+                               dim3(kBlock), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_ALL>), dim3(grid), dim3(kBlock), 0, s, a);
+        }
         return hipGetLastError();
     }
     static hipError_t observe(const KArgs &a, int grid, hipStream_t s)

@@ -69,18 +69,23 @@ def main(argv=None):
     copy_key = max((k for k in fetch if k[0] == COPY_KERNEL), key=lambda k: fetch[k])
     f_scale = a.copy_bytes / (fetch[copy_key] * 1024.0)
     w_scale = a.copy_bytes / (write[copy_key] * 1024.0)
-    step_key = [k for k in fetch if "step_kernel" in k[0]][0]
-    step_stat = [s for s in stats if "step_kernel" in s["name"]][0]
-    fb = fetch[step_key] * 1024.0 * f_scale
-    wb = write[step_key] * 1024.0 * w_scale
+    # a time step may be more than one launch (16-bit storage with walls:
+    # interior rows and wall rows): sum the step kernels
+    step_keys = [k for k in fetch if "step_kernel" in k[0]]
+    step_stats = [s for s in stats if "step_kernel" in s["name"]]
+    avg_us = sum(s["avg_us"] for s in step_stats)
+    fkib = sum(fetch[k] for k in step_keys)
+    wkib = sum(write.get(k, 0.0) for k in step_keys)
+    fb = fkib * 1024.0 * f_scale
+    wb = wkib * 1024.0 * w_scale
     rec = {
-        "kernel": step_key[0], "grid": step_key[1], "avg_duration_us": step_stat["avg_us"],
-        "fetch_kib_raw": fetch[step_key], "write_kib_raw": write[step_key],
+        "kernel": " + ".join(k[0] for k in step_keys), "grid": [k[1] for k in step_keys], "avg_duration_us": avg_us,
+        "fetch_kib_raw": fkib, "write_kib_raw": wkib,
         "fetch_scale": f_scale, "write_scale": w_scale,
         "hbm_fetch_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb,
         "hbm_bytes_per_launch": fb + wb, "algorithmic_bytes_per_launch": a.algorithmic_bytes,
         "traffic_over_algorithmic": (fb + wb) / a.algorithmic_bytes,
-        "hbm_GBs": (fb + wb) / (step_stat["avg_us"] * 1e-6) / 1e9,
+        "hbm_GBs": (fb + wb) / (avg_us * 1e-6) / 1e9,
     }
     os.makedirs(PROFILES, exist_ok=True)
     tpath = os.path.join(PROFILES, "traffic_%s.json" % a.workload)
@@ -109,7 +114,7 @@ def main(argv=None):
             fh.write("| `%s` | %d | %.1f | %.1f |\n" % (k[0][:60], k[1], fetch.get(k, float("nan")), write.get(k, float("nan"))))
         fh.write("\nCalibration: the %d-byte device copy (`%s`) reads FETCH_SIZE x %.3f and WRITE_SIZE x %.3f "
                  "of its true bytes.\n\n" % (a.copy_bytes, COPY_KERNEL, 1 / f_scale, 1 / w_scale))
-        fh.write("## Step kernel per launch\n\n")
+        fh.write("## Step kernel(s) per time step\n\n")
         fh.write("- average duration: %.1f us\n" % rec["avg_duration_us"])
         fh.write("- HBM bytes (scaled counters): fetch %.4g, write %.4g, total %.4g\n" % (fb, wb, fb + wb))
         fh.write("- algorithmic bytes 2 Q s per node: %.4g (traffic / algorithmic = %.3f)\n"
