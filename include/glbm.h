@@ -154,6 +154,44 @@ int glbm_destroy(glbm_t *h);
 /* Message of the last failing call on this thread ("" if none). */
 const char *glbm_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batched stepping: many solvers advanced together (uneven sizes, levels and
+ * parameters).  Members of the same kernel variant (levels, storage,
+ * boundaries) share one launch per step over a table of tiles, each tile a
+ * run of nodes of one member; a chunk of steps is captured once into a HIP
+ * graph and replayed.  Every node runs exactly the code of glbm_step, so a
+ * member's populations are bitwise those of the member stepped alone
+ * (stochastic-rounding seeds included).
+ * ------------------------------------------------------------------------ */
+#define GLBM_ORDER_MEMBER 0        /* tiles of each member contiguous */
+#define GLBM_ORDER_INTERLEAVE 1    /* tiles dealt round-robin over the members */
+#define GLBM_ORDER_LARGEST_FIRST 2 /* members by decreasing work, contiguous */
+
+typedef struct glbm_batch_options {
+    int32_t tile_nodes;  /* nodes per workgroup: 64, 128 or 256 (0 = 256) */
+    int32_t order;       /* GLBM_ORDER_* */
+    int32_t graph_steps; /* steps per captured HIP graph; 0 = plain launches */
+} glbm_batch_options;
+
+typedef struct glbm_batch glbm_batch_t;
+
+/* Group n >= 1 initialised solvers (host array of handles, each at most once,
+ * all on the current device) into a batch that launches on `stream` (NULL =
+ * the default stream, joined through events).  While a solver belongs to a
+ * batch, glbm_step on it returns GLBM_ERR_STATE; glbm_moments, glbm_stats and
+ * glbm_get_populations keep working (on the solver's own stream: synchronise
+ * the two streams if they differ).  opt may be NULL (defaults).  Small device
+ * tables are allocated here and released by glbm_batch_destroy. */
+int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_options *opt, void *stream,
+                      glbm_batch_t **out);
+
+/* Advance every member by nsteps >= 0 steps. */
+int glbm_batch_step(glbm_batch_t *b, int64_t nsteps);
+
+/* Release the batch (members stay valid and can be stepped alone again).
+ * Waits for the batch's work. */
+int glbm_batch_destroy(glbm_batch_t *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,9 +5,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/glbm.h"
 #include "glbm_internal.h"
@@ -117,15 +119,7 @@ int check_config(const glbm_config *c, Geometry *g)
     return GLBM_OK;
 }
 
-// Seed of the stochastic rounding for the step that produces time t.
-uint32_t step_seed(int64_t t)
-{
-    uint64_t x = (uint64_t)t * 0x9e3779b97f4a7c15ULL + 0x632be59bd9b4e019ULL;
-    x ^= x >> 31;
-    x *= 0xbf58476d1ce4e5b9ULL;
-    x ^= x >> 29;
-    return (uint32_t)(x >> 32);
-}
+__global__ void bump_counter(int64_t *c, int64_t k) { *c += k; }
 
 __global__ void reduce_partials(const double *partials, int nblocks, double *out)
 {
@@ -167,6 +161,7 @@ struct glbm_solver {
     int grid;
     double *d_partials, *d_out, *h_out;
     int device;
+    bool in_batch;
 };
 
 extern "C" {
@@ -217,6 +212,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     h->cur = 0;
     h->t = 0;
     h->ready = false;
+    h->in_batch = false;
     h->stream = (hipStream_t)stream;
     h->var = v;
     (void)hipGetDevice(&h->device);
@@ -306,6 +302,7 @@ int glbm_step(glbm_t *h, int64_t nsteps)
 {
     if (!h) return fail(GLBM_ERR_INVALID, "handle is NULL");
     if (!h->ready) return fail(GLBM_ERR_STATE, "step before init");
+    if (h->in_batch) return fail(GLBM_ERR_STATE, "the solver belongs to a batch: step the batch");
     if (nsteps < 0) return fail(GLBM_ERR_INVALID, "nsteps must be >= 0");
     KArgs a = h->base;
     for (int64_t s = 0; s < nsteps; ++s) {
@@ -395,11 +392,243 @@ int glbm_info(const glbm_t *h, double *tau, double *omega, int32_t *nvel, int64_
 int glbm_destroy(glbm_t *h)
 {
     if (!h) return GLBM_OK;
+    if (h->in_batch) return fail(GLBM_ERR_STATE, "the solver belongs to a batch: destroy the batch first");
     (void)hipStreamSynchronize(h->stream);
     (void)hipFree(h->d_partials);
     (void)hipFree(h->d_out);
     (void)hipHostFree(h->h_out);
     delete h;
+    return GLBM_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct glbm_batch {
+    struct RowSet {
+        const Variant *var;
+        int rows;            // StepRows
+        BatchTile *d_tiles;  // device tile table
+        int ntiles;
+    };
+    std::vector<glbm_solver *> members;
+    std::vector<RowSet> sets;
+    hipStream_t user;     // caller's stream (may be NULL)
+    hipStream_t exec;     // stream the batch launches on
+    bool own_stream;
+    hipEvent_t ev_in, ev_out;
+    KArgs *d_args;
+    int32_t *d_phase;
+    int64_t *d_t0, *d_bstep;
+    int block, graph_k;
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+};
+
+static void batch_free(glbm_batch *b)
+{
+    for (auto &r : b->sets) (void)hipFree(r.d_tiles);
+    (void)hipFree(b->d_args);
+    (void)hipFree(b->d_phase);
+    (void)hipFree(b->d_t0);
+    (void)hipFree(b->d_bstep);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->own_stream) (void)hipStreamDestroy(b->exec);
+    for (auto *m : b->members) m->in_batch = false;
+    delete b;
+}
+
+// One chunk of k steps: launches l = 0..k-1 of every row set, then the device
+// step counter advances by k.
+static hipError_t batch_chunk(glbm_batch *b, int k)
+{
+    for (int l = 0; l < k; ++l)
+        for (auto &r : b->sets) {
+            hipError_t e = r.var->batch(r.rows, r.d_tiles, r.ntiles, b->block, b->d_args, b->d_phase, b->d_t0,
+                                        b->d_bstep, l, b->exec);
+            if (e != hipSuccess) return e;
+        }
+    hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->exec, b->d_bstep, (int64_t)k);
+    return hipGetLastError();
+}
+
+extern "C" {
+
+int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_options *opt, void *stream,
+                      glbm_batch_t **out)
+{
+    if (!out) return fail(GLBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    glbm_batch_options o = {256, GLBM_ORDER_MEMBER, 0};
+    if (opt) o = *opt;
+    if (o.tile_nodes == 0) o.tile_nodes = 256;
+    if (o.tile_nodes != 64 && o.tile_nodes != 128 && o.tile_nodes != 256)
+        return fail(GLBM_ERR_INVALID, "tile_nodes must be 64, 128 or 256");
+    if (o.order < GLBM_ORDER_MEMBER || o.order > GLBM_ORDER_LARGEST_FIRST)
+        return fail(GLBM_ERR_INVALID, "unknown tile order");
+    if (o.graph_steps < 0) return fail(GLBM_ERR_INVALID, "graph_steps must be >= 0");
+    if (!members || n < 1) return fail(GLBM_ERR_INVALID, "a batch needs at least one member");
+    for (int i = 0; i < n; ++i) {
+        glbm_solver *m = members[i];
+        if (!m) return fail(GLBM_ERR_INVALID, "member %d is NULL", i);
+        if (!m->ready) return fail(GLBM_ERR_STATE, "member %d is not initialised", i);
+        if (m->in_batch) return fail(GLBM_ERR_STATE, "member %d already belongs to a batch", i);
+        for (int j = 0; j < i; ++j)
+            if (members[j] == m) return fail(GLBM_ERR_INVALID, "member %d appears twice", i);
+    }
+
+    glbm_batch *b = new (std::nothrow) glbm_batch();
+    if (!b) return fail(GLBM_ERR_INVALID, "out of host memory");
+    b->members.assign(members, members + n);
+    b->block = o.tile_nodes;
+    b->graph_k = o.graph_steps;
+    b->user = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (b->user) {
+        b->exec = b->user;
+    } else {
+        e = hipStreamCreateWithFlags(&b->exec, hipStreamNonBlocking);
+        b->own_stream = e == hipSuccess;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    }
+
+    // per-member arguments for both parities, phase and time origin
+    std::vector<KArgs> args(2 * (size_t)n);
+    std::vector<int32_t> phase(n);
+    std::vector<int64_t> t0(n);
+    for (int i = 0; i < n; ++i) {
+        glbm_solver *m = members[i];
+        for (int c = 0; c < 2; ++c) {
+            KArgs a = m->base;
+            a.src = m->buf[c];
+            a.dst = m->buf[1 - c];
+            a.remap = 0;
+            args[2 * i + c] = a;
+        }
+        phase[i] = m->cur;
+        t0[i] = m->t;
+    }
+    const int64_t zero = 0;
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_args, sizeof(KArgs) * args.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_phase, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_t0, sizeof(int64_t) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_bstep, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMemcpy(b->d_args, args.data(), sizeof(KArgs) * args.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_phase, phase.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_t0, t0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_bstep, &zero, sizeof(int64_t), hipMemcpyHostToDevice);
+
+    // tile tables per (variant, row set)
+    struct Part {
+        int member, count;
+        double work;
+    };
+    std::vector<const Variant *> vars;
+    for (auto *m : b->members)
+        if (std::find(vars.begin(), vars.end(), m->var) == vars.end()) vars.push_back(m->var);
+    for (const Variant *v : vars) {
+        const int rowsets[2][2] = {{ROWS_INTERIOR, ROWS_WALLS}, {ROWS_ALL, -1}};
+        for (int rsi = 0; rsi < 2 && e == hipSuccess; ++rsi) {
+            const int rows = rowsets[v->split_rows ? 0 : 1][rsi];
+            if (rows < 0) break;
+            std::vector<Part> parts;
+            for (int i = 0; i < n; ++i) {
+                glbm_solver *m = members[i];
+                if (m->var != v) continue;
+                const int64_t nx = m->geo.nx, ny = m->geo.ny, ly = m->geo.ly;
+                const int64_t cnt = rows == ROWS_ALL ? nx * ny : rows == ROWS_INTERIOR ? (ny - 2 * ly) * nx : 2 * ly * nx;
+                if (cnt > 0) parts.push_back({i, (int)cnt, (double)cnt * m->geo.q});
+            }
+            if (o.order == GLBM_ORDER_LARGEST_FIRST)
+                std::stable_sort(parts.begin(), parts.end(), [](const Part &x, const Part &y) { return x.work > y.work; });
+            std::vector<BatchTile> tiles;
+            if (o.order == GLBM_ORDER_INTERLEAVE) {
+                for (int first = 0;; first += o.tile_nodes) {
+                    bool any = false;
+                    for (const Part &pt : parts)
+                        if (first < pt.count) {
+                            tiles.push_back({pt.member, first, std::min(o.tile_nodes, pt.count - first), 0});
+                            any = true;
+                        }
+                    if (!any) break;
+                }
+            } else {
+                for (const Part &pt : parts)
+                    for (int first = 0; first < pt.count; first += o.tile_nodes)
+                        tiles.push_back({pt.member, first, std::min(o.tile_nodes, pt.count - first), 0});
+            }
+            if (tiles.empty()) continue;
+            glbm_batch::RowSet r{v, rows, nullptr, (int)tiles.size()};
+            e = hipMalloc((void **)&r.d_tiles, sizeof(BatchTile) * tiles.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(r.d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice);
+            b->sets.push_back(r);
+        }
+    }
+
+    // capture one chunk of graph_k steps
+    if (e == hipSuccess && b->graph_k > 0) {
+        e = hipStreamBeginCapture(b->exec, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t ec = batch_chunk(b, b->graph_k);
+            e = hipStreamEndCapture(b->exec, &b->graph);
+            if (ec != hipSuccess) e = ec;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "creating the batch");
+    }
+    for (auto *m : b->members) m->in_batch = true;
+    *out = b;
+    return GLBM_OK;
+}
+
+int glbm_batch_step(glbm_batch_t *b, int64_t nsteps)
+{
+    if (!b) return fail(GLBM_ERR_INVALID, "batch is NULL");
+    if (nsteps < 0) return fail(GLBM_ERR_INVALID, "nsteps must be >= 0");
+    if (nsteps == 0) return GLBM_OK;
+    hipError_t e = hipSuccess;
+    if (b->own_stream) {
+        // order after the caller's earlier work on the default stream
+        e = hipEventRecord(b->ev_in, b->user);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->exec, b->ev_in, 0);
+    }
+    int64_t left = nsteps;
+    while (e == hipSuccess && b->graph_exec && left >= b->graph_k) {
+        e = hipGraphLaunch(b->graph_exec, b->exec);
+        left -= b->graph_k;
+    }
+    while (e == hipSuccess && left > 0) {
+        const int k = (int)std::min<int64_t>(left, 1 << 20);
+        e = batch_chunk(b, k);
+        left -= k;
+    }
+    if (e == hipSuccess && b->own_stream) {
+        e = hipEventRecord(b->ev_out, b->exec);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->user, b->ev_out, 0);
+    }
+    if (e != hipSuccess) return hip_fail(e, "stepping the batch");
+    for (auto *m : b->members) {
+        m->t += nsteps;
+        if (nsteps & 1) m->cur = 1 - m->cur;
+    }
+    return GLBM_OK;
+}
+
+int glbm_batch_destroy(glbm_batch_t *b)
+{
+    if (!b) return GLBM_OK;
+    (void)hipStreamSynchronize(b->exec);
+    batch_free(b);
     return GLBM_OK;
 }
 

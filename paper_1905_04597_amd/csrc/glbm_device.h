@@ -565,9 +565,20 @@ __device__ __forceinline__ void store_node(const KArgs &p, rsrc_t rd, int x, int
 
 // Hash of (node, step) for the stochastic rounding: reproducible, independent
 // of the launch shape.
-__device__ __forceinline__ uint32_t node_hash(const KArgs &p, int i)
+__device__ __forceinline__ uint32_t node_hash(uint32_t seed, int i)
 {
-    return mix32((uint32_t)i ^ p.seed);
+    return mix32((uint32_t)i ^ seed);
+}
+
+// Seed of the stochastic rounding for the step that produces time t (host and
+// device: a batched lattice draws the same bits as the lattice alone).
+__host__ __device__ inline uint32_t step_seed(int64_t t)
+{
+    uint64_t x = (uint64_t)t * 0x9e3779b97f4a7c15ULL + 0x632be59bd9b4e019ULL;
+    x ^= x >> 31;
+    x *= 0xbf58476d1ce4e5b9ULL;
+    x ^= x >> 29;
+    return (uint32_t)(x >> 32);
 }
 
 // ------------------------------------------------------------- kernels
@@ -618,32 +629,21 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
 // emission, or the LY rows next to each wall.
 enum StepRows { ROWS_ALL = 0, ROWS_INTERIOR = 1, ROWS_WALLS = 2 };
 
-// One time step: pull from f*(t-1), collide, write f*(t).  With 16-bit
-// storage the populations stay packed in registers (PackedRegs) wherever no
-// wall emission enters; the wall rows of such a lattice are a separate launch
-// (ROWS_WALLS, FP32 registers, so that emitted populations enter the collision
-// unrounded), which keeps the packed kernel's register allocation its own.
+// One time step of node i: pull from f*(t-1), collide, write f*(t).  With
+// 16-bit storage the populations stay packed in registers (PackedRegs)
+// wherever no wall emission enters (ROWS_INTERIOR); the wall rows of such a
+// lattice are a separate launch (ROWS_WALLS, FP32 registers, so that emitted
+// populations enter the collision unrounded), which keeps the packed
+// kernel's register allocation its own.
 template <int LX, int LY, int ST, int BCX, int BCY, int ROWS>
-__global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
+__device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
 {
     using L = Lat<LX, LY, ST>;
-    int i = tile_index(p) * kBlock + (int)threadIdx.x;
-    int y, x;
-    if constexpr (ROWS == ROWS_ALL) {
-        if (i >= p.nodes) return;
-    } else if constexpr (ROWS == ROWS_INTERIOR) {
-        if (i >= (p.ny - 2 * LY) * p.nx) return;
-        i += LY * p.nx;
-    } else {
-        if (i >= 2 * LY * p.nx) return;
-        if (i >= LY * p.nx) i += (p.ny - 2 * LY) * p.nx;
-    }
-    y = i / p.nx;
-    x = i - y * p.nx;
+    const int y = i / p.nx, x = i - y * p.nx;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
-    const uint32_t h = ST == ST_BF16SR ? node_hash(p, i) : 0u;
-    if constexpr (L::EB == 2 && ROWS != ROWS_WALLS) {
+    const uint32_t h = ST == ST_BF16SR ? node_hash(seed, i) : 0u;
+    if constexpr (L::EB == 2 && ROWS == ROWS_INTERIOR) {
         step_packed<LX, LY, ST, BCX, BCY>(p, rs, rd, x, y, h);
     } else {
         float v[L::QY][L::QX];
@@ -654,6 +654,56 @@ __global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
         collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
         store_node<LX, LY, ST, BCX>(p, rd, x, y, v, h);
     }
+}
+
+// Node index of launch index i for a set of rows (see StepRows); -1 outside.
+template <int LY, int ROWS>
+__device__ __forceinline__ int row_set_node(int i, int nx, int ny)
+{
+    if constexpr (ROWS == ROWS_ALL) {
+        return i < nx * ny ? i : -1;
+    } else if constexpr (ROWS == ROWS_INTERIOR) {
+        return i < (ny - 2 * LY) * nx ? i + LY * nx : -1;
+    } else {
+        if (i >= 2 * LY * nx) return -1;
+        return i < LY * nx ? i : i + (ny - 2 * LY) * nx;
+    }
+}
+
+template <int LX, int LY, int ST, int BCX, int BCY, int ROWS>
+__global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
+{
+    const int i = row_set_node<LY, ROWS>(tile_index(p) * kBlock + (int)threadIdx.x, p.nx, p.ny);
+    if (i < 0) return;
+    step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, p.seed);
+}
+
+// Batched step: many lattices of one variant in one launch.  Block b takes
+// tile b = (member, first launch index, count) of the table; the member's
+// arguments for this launch's parity are read through the scalar unit, and
+// the node runs exactly the single-lattice code, so that a batched lattice is
+// bitwise the lattice stepped alone.
+struct BatchTile {
+    int32_t member, first, count, pad;
+};
+
+// Launch `launch` of a chunk: batch step s = *bstep + launch; member m is at
+// time t0[m] + s, its f*(t) in buffer phase[m] ^ (s & 1).  args holds two
+// argument sets per member, args[2m + c] pulling from buffer c.
+template <int LX, int LY, int ST, int BCX, int BCY, int ROWS>
+__global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchTile *__restrict__ tiles,
+                                                            const KArgs *__restrict__ args,
+                                                            const int32_t *__restrict__ phase,
+                                                            const int64_t *__restrict__ t0,
+                                                            const int64_t *__restrict__ bstep, int32_t launch)
+{
+    const BatchTile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const int64_t s = *bstep + launch;
+    const KArgs &p = args[2 * t.member + (phase[t.member] ^ (int)(s & 1))];
+    const int i = row_set_node<LY, ROWS>(t.first + (int)threadIdx.x, p.nx, p.ny);
+    if (i < 0) return;
+    step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, ST == ST_BF16SR ? step_seed(t0[t.member] + s + 1) : 0u);
 }
 
 // Moments (and optionally the populations) of the pre-collision state f(t).
@@ -766,7 +816,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(KArgs p)
             });
         });
     }
-    const uint32_t h = ST == ST_BF16SR ? node_hash(p, i) : 0u;
+    const uint32_t h = ST == ST_BF16SR ? node_hash(p.seed, i) : 0u;
     if constexpr (Elem<ST>::bytes == 2) {
         // round f(0) as the storage will, so that f*(0) is the collision of the
         // stored f(0) (the stores below are then exact)

@@ -43,6 +43,20 @@ struct Launchers {
         hipLaunchKernelGGL((ends_kernel<LX, LY, ST>), dim3(grid), dim3(kBlock), 0, s, a, rl, rr);
         return hipGetLastError();
     }
+    static hipError_t batch(int rows, const BatchTile *tiles, int ntiles, int block, const KArgs *args,
+                            const int32_t *phase, const int64_t *t0, const int64_t *bstep, int launch, hipStream_t s)
+    {
+        if (rows == ROWS_INTERIOR)
+            hipLaunchKernelGGL((batch_step_kernel<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>), dim3(ntiles), dim3(block), 0,
+                               s, tiles, args, phase, t0, bstep, launch);
+        else if (rows == ROWS_WALLS)
+            hipLaunchKernelGGL((batch_step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>), dim3(ntiles), dim3(block), 0, s,
+                               tiles, args, phase, t0, bstep, launch);
+        else
+            hipLaunchKernelGGL((batch_step_kernel<LX, LY, ST, BCX, BCY, ROWS_ALL>), dim3(ntiles), dim3(block), 0, s,
+                               tiles, args, phase, t0, bstep, launch);
+        return hipGetLastError();
+    }
     static void add()
     {
         Variant *v = variant_slot(LX, LY, ST, BCX, BCY);
@@ -51,6 +65,8 @@ struct Launchers {
         v->init = &init;
         v->stats = &stats;
         v->ends = BCX == BCX_EQ ? &ends : nullptr;
+        v->batch = &batch;
+        v->split_rows = Elem<ST>::bytes == 2 && BCY == BCY_WALL;
     }
 };
 

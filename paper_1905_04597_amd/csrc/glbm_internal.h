@@ -10,6 +10,10 @@ namespace glbm {
 
 using Launch = hipError_t (*)(const KArgs &, int grid, hipStream_t);
 using LaunchEnds = hipError_t (*)(const KArgs &, int grid, float, float, hipStream_t);
+// Batched step over a tile table for one row set (StepRows).
+using LaunchBatch = hipError_t (*)(int rows, const BatchTile *tiles, int ntiles, int block, const KArgs *args,
+                                   const int32_t *phase, const int64_t *t0, const int64_t *bstep, int launch,
+                                   hipStream_t);
 
 // Kernels of one (level_x, level_y, storage, bc_x, bc_y) variant.
 struct Variant {
@@ -18,6 +22,8 @@ struct Variant {
     Launch init = nullptr;
     Launch stats = nullptr;
     LaunchEnds ends = nullptr;
+    LaunchBatch batch = nullptr;
+    bool split_rows = false;  // steps run as interior rows + wall rows (16-bit storage with walls)
 };
 
 // Registry of built variants, indexed by levels (0..kMaxLevel), storage, bc_x, bc_y.

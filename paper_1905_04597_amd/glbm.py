@@ -23,8 +23,9 @@ MAX_LEVEL = 7
 SYMBOLS = (
     "glbm_population_bytes", "glbm_create", "glbm_init_fields", "glbm_init_populations",
     "glbm_step", "glbm_moments", "glbm_get_populations", "glbm_stats", "glbm_info",
-    "glbm_destroy", "glbm_last_error",
+    "glbm_destroy", "glbm_last_error", "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy",
 )
+ORDER = {"member": 0, "interleave": 1, "largest_first": 2}
 
 
 class GlbmError(RuntimeError):
@@ -46,6 +47,14 @@ class Config(ctypes.Structure):
         ("wall_u", ctypes.c_double * 2),
         ("end_rho", ctypes.c_double * 2),
         ("g", ctypes.c_double),
+    ]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [
+        ("tile_nodes", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int32),
     ]
 
 
@@ -90,8 +99,13 @@ def load(path: str = LIB_PATH):
     lib.glbm_destroy.argtypes = [vp]
     lib.glbm_last_error.argtypes = []
     lib.glbm_last_error.restype = ctypes.c_char_p
+    lib.glbm_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(BatchOptions), vp,
+                                      ctypes.POINTER(vp)]
+    lib.glbm_batch_step.argtypes = [vp, ctypes.c_int64]
+    lib.glbm_batch_destroy.argtypes = [vp]
     for name in ("glbm_init_fields", "glbm_init_populations", "glbm_step", "glbm_moments",
-                 "glbm_get_populations", "glbm_stats", "glbm_info", "glbm_destroy"):
+                 "glbm_get_populations", "glbm_stats", "glbm_info", "glbm_destroy",
+                 "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -237,7 +251,56 @@ class Solver:
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            self.lib.glbm_destroy(h)
+            _check(self.lib.glbm_destroy(h), "glbm_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many solvers stepped together (glbm_batch_*): one launch per kernel
+    variant and step over a tile table, optionally replayed from a captured
+    HIP graph of ``graph_steps`` steps.  Members keep their own buffers and
+    can be observed while in the batch; ``close()`` hands them back."""
+
+    def __init__(self, solvers, tile_nodes: int = 256, order: str = "member", graph_steps: int = 0, stream=None):
+        import torch
+
+        if not solvers:
+            raise GlbmError("a batch needs at least one solver")
+        self._torch = torch
+        self.lib = load()
+        self.solvers = list(solvers)
+        self.device = self.solvers[0].device
+        self.stream = stream if stream is not None else self.solvers[0].stream
+        self.options = {"tile_nodes": int(tile_nodes), "order": order, "graph_steps": int(graph_steps)}
+        opt = BatchOptions(int(tile_nodes), ORDER[order], int(graph_steps))
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s._h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.glbm_batch_create(arr, len(self.solvers), ctypes.byref(opt),
+                                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                   "glbm_batch_create")
+        self._h = h
+
+    def step(self, n: int = 1):
+        with self._torch.cuda.device(self.device):
+            _check(self.lib.glbm_batch_step(self._h, int(n)), "glbm_batch_step")
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.glbm_batch_destroy(h)
             self._h = None
 
     def __del__(self):

@@ -137,5 +137,30 @@ def batch_sweep(count: int = 512, seed: int = 190504597, steps: int = 2000):
     return out
 
 
+def sweep_workloads(count: int = 512, seed: int = 190504597, steps: int = 2000,
+                    storage: str = "f32_shifted"):
+    """The batched sweep as Workload objects (same draw as batch_sweep).
+
+    Couette: walls at -/+ speed.  Poiseuille: walls at rest and the force
+    that gives the drawn centre-line speed in the continuum limit,
+    g = 8 nu U / H^2 with H = Ny, nu = theta tau, theta = N / 3 and the
+    relaxation time that the Knudsen number sets, tau = Kn H / sqrt(2 theta)
+    (an input recipe: the solvers derive tau from Kn themselves)."""
+    out = []
+    for d in batch_sweep(count, seed, steps):
+        if d["kind"] == "couette":
+            w = couette(d["kn"], ny=d["ny"], nx=d["nx"], level=d["level"], steps=steps, storage=storage)
+            w.wall_u = (-d["speed"], d["speed"])
+        else:
+            theta = d["level"] / 3.0
+            H = float(d["ny"])
+            nu = theta * d["kn"] * H / math.sqrt(2.0 * theta)
+            w = poiseuille(nx=d["nx"], ny=d["ny"], level=d["level"], kn=d["kn"],
+                           g=8.0 * nu * d["speed"] / (H * H), steps=steps, storage=storage)
+        w.name = "%s_%d" % (w.name, d["index"])
+        out.append(w)
+    return out
+
+
 def maybe_f64(a: Optional[np.ndarray]):
     return None if a is None else np.asarray(a, dtype=np.float64)

@@ -72,3 +72,22 @@ def test_create_rejects_missing_buffers_without_touching_the_gpu():
     assert lib.glbm_create(ctypes.byref(c), None, None, None, ctypes.byref(h)) == -1
     assert "buffers" in lib.glbm_last_error().decode()
     assert lib.glbm_step(None, 1) == -1
+
+
+def test_batch_entry_points_reject_bad_arguments_without_touching_the_gpu():
+    lib = glbm.load()
+    out = ctypes.c_void_p()
+    opt = glbm.BatchOptions(96, 0, 0)
+    assert lib.glbm_batch_create(None, 0, ctypes.byref(opt), None, ctypes.byref(out)) == -1
+    assert "tile_nodes" in lib.glbm_last_error().decode()
+    opt = glbm.BatchOptions(128, 7, 0)
+    assert lib.glbm_batch_create(None, 0, ctypes.byref(opt), None, ctypes.byref(out)) == -1
+    assert "order" in lib.glbm_last_error().decode()
+    opt = glbm.BatchOptions(128, 1, -1)
+    assert lib.glbm_batch_create(None, 0, ctypes.byref(opt), None, ctypes.byref(out)) == -1
+    assert "graph_steps" in lib.glbm_last_error().decode()
+    assert lib.glbm_batch_create(None, 0, None, None, ctypes.byref(out)) == -1
+    assert "at least one member" in lib.glbm_last_error().decode()
+    assert lib.glbm_batch_create(None, 1, None, None, None) == -1
+    assert lib.glbm_batch_step(None, 1) == -1
+    assert lib.glbm_batch_destroy(None) == 0

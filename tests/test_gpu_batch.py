@@ -1,0 +1,161 @@
+"""Batched stepping (glbm_batch_*) against the same lattices stepped alone.
+
+Every node of a batched member runs the code of glbm_step with the same
+stochastic-rounding seeds, so the populations must be bitwise equal to the
+member stepped on its own, for every storage, boundary kind, tile size, tile
+order and graph chunking (including a remainder after the last whole
+graph), and for members that join the batch at different times and buffer
+phases.  Stepping alone is itself checked against the oracle by the parity
+tests; one batched member is also compared with the oracle directly.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_04597_amd import batching, glbm
+from paper_1905_04597_amd import workloads as wl
+from tests.gpu_common import compare_moments, fmt, gpu_moments, initialise, make_pair
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [
+    dict(dims=2, level_x=3, level_y=3, nx=4, ny=37, kn=0.1, bc_y="wall", wall_u=(-0.05, 0.05), storage="f32_shifted"),
+    dict(dims=2, level_x=5, level_y=5, nx=70, ny=23, kn=1.0, bc_y="wall", g=1e-5, storage="f32_shifted"),
+    dict(dims=2, level_x=2, level_y=2, nx=130, ny=9, tau=0.8, storage="f32_shifted"),
+    dict(dims=2, level_x=4, level_y=4, nx=4, ny=64, kn=0.01, bc_y="wall", g=2e-5, storage="f32"),
+    dict(dims=2, level_x=3, level_y=3, nx=33, ny=41, kn=0.1, bc_y="wall", wall_u=(0.02, 0.03),
+         storage="bf16_shifted_sr"),
+    dict(dims=2, level_x=3, level_y=3, nx=4, ny=100, kn=0.3, bc_y="wall", g=1e-5, storage="bf16_shifted_sr"),
+    dict(dims=1, level_x=3, nx=300, kn=0.01, bc_x="eq_ends", end_rho=(1.0, 0.125), storage="f32_shifted"),
+    dict(dims=2, level_x=1, level_y=4, nx=50, ny=30, kn=0.1, bc_y="wall", wall_u=(0.0, 0.04), storage="f32_shifted"),
+    dict(dims=2, level_x=3, level_y=3, nx=4, ny=37, kn=0.05, bc_y="wall", wall_u=(-0.03, 0.05), storage="f32_shifted"),
+]
+
+
+def _solver(cfg):
+    return glbm.Solver(glbm.make_config(**cfg))
+
+
+def _init(s, cfg, seed):
+    if cfg["dims"] == 1 and cfg.get("bc_x") == "eq_ends":
+        rho = wl.sod_density(cfg["nx"], *cfg["end_rho"])
+        s.init_fields(rho, np.zeros_like(rho))
+    else:
+        rho, ux, uy = wl.random_fields(seed, cfg["nx"], cfg.get("ny", 1), rho_amp=0.05, u_amp=0.05, dims=cfg["dims"])
+        s.init_fields(rho, ux, uy if cfg["dims"] == 2 else None)
+
+
+def _pair(cfgs):
+    alone, batched = [], []
+    for i, cfg in enumerate(cfgs):
+        a, b = _solver(cfg), _solver(cfg)
+        _init(a, cfg, 100 + i)
+        _init(b, cfg, 100 + i)
+        # members join at different times and buffer phases
+        a.step(i % 3)
+        b.step(i % 3)
+        alone.append(a)
+        batched.append(b)
+    return alone, batched
+
+
+def _assert_bitwise(alone, batched, what):
+    import torch
+
+    for i, (a, b) in enumerate(zip(alone, batched)):
+        pa, pb = a.populations(), b.populations()
+        same = torch.equal(pa, pb)
+        if not same:
+            diff = (pa - pb).abs().max().item()
+            print("[batch] %s member %d differs: max |df| %.3e" % (what, i, diff), flush=True)
+        assert same, (what, i)
+        assert a.info()["time"] == b.info()["time"]
+
+
+@pytest.mark.parametrize("opts", [
+    dict(tile_nodes=256, order="member", graph_steps=0),
+    dict(tile_nodes=64, order="interleave", graph_steps=8),
+    dict(tile_nodes=128, order="largest_first", graph_steps=5),
+])
+def test_batch_bitwise_equals_alone(opts):
+    print("\n[batch] mixed members, options %s" % opts, flush=True)
+    alone, batched = _pair(MEMBERS)
+    with glbm.Batch(batched, **opts) as b:
+        b.step(19)
+        b.step(0)
+        b.step(4)
+    for s in alone:
+        s.step(23)
+    _assert_bitwise(alone, batched, "after the batch")
+    # members leave the batch and continue alone
+    for s in alone + batched:
+        s.step(3)
+    _assert_bitwise(alone, batched, "after leaving the batch")
+
+
+def test_member_of_a_batch_cannot_step_alone():
+    s = _solver(MEMBERS[0])
+    _init(s, MEMBERS[0], 1)
+    b = glbm.Batch([s])
+    with pytest.raises(glbm.GlbmError, match="batch"):
+        s.step(1)
+    with pytest.raises(glbm.GlbmError, match="batch"):
+        s.close()
+    with pytest.raises(glbm.GlbmError, match="already belongs"):
+        glbm.Batch([s])
+    b.step(2)
+    b.close()
+    s.step(1)
+    assert s.info()["time"] == 3
+    s.close()
+
+
+def test_batch_rejects_duplicates_and_uninitialised():
+    s = _solver(MEMBERS[0])
+    with pytest.raises(glbm.GlbmError, match="not initialised"):
+        glbm.Batch([s])
+    _init(s, MEMBERS[0], 1)
+    with pytest.raises(glbm.GlbmError, match="twice"):
+        glbm.Batch([s, s])
+    s.close()
+
+
+@pytest.mark.parametrize("storage", ["f32_shifted", "bf16_shifted_sr"])
+def test_sweep_subset_bitwise(storage):
+    """The first 24 instances of the 512-instance channel sweep (uneven Ny,
+    levels 2..6, Couette and force-driven Poiseuille), 50 steps."""
+    ws = wl.sweep_workloads(storage=storage)[:24]
+    print("\n[batch] sweep subset, %d instances, storage %s" % (len(ws), storage), flush=True)
+    alone = [glbm.solver_for(w) for w in ws]
+    batched = [glbm.solver_for(w) for w in ws]
+    for s in alone + batched:
+        s.init_fields()
+    with glbm.Batch(batched, tile_nodes=128, order="interleave", graph_steps=16) as b:
+        b.step(50)
+    for s in alone:
+        s.step(50)
+    _assert_bitwise(alone, batched, "sweep subset")
+
+
+def test_batched_member_against_oracle():
+    """A Couette member stepped inside a batch of other lattices, against the
+    oracle (FP32 deviation storage, 1e-5)."""
+    params = dict(dims=2, level_x=3, level_y=3, nx=4, ny=48, kn=0.1, bc_y="wall", wall_u=(-0.05, 0.05))
+    orc, gpu = make_pair(params, "f32_shifted")
+    initialise(orc, gpu, "fields", seed=11)
+    others = [_solver(c) for c in MEMBERS[1:4]]
+    for i, s in enumerate(others):
+        _init(s, MEMBERS[1 + i], 7 + i)
+    with glbm.Batch([gpu] + others, tile_nodes=64, order="interleave", graph_steps=10) as b:
+        b.step(40)
+    orc.step(40)
+    errs = compare_moments(orc.moments(), gpu_moments(gpu), 1.0)
+    print("[batch] batched Couette member vs oracle at t=40: %s" % fmt(errs), flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_autotune_returns_a_candidate():
+    cfgs = [glbm.make_config(**c) for c in MEMBERS[:4]]
+    cands = batching.candidates(tiles=(64, 256), orders=("member", "interleave"), graphs=(0, 8))
+    best, results = batching.autotune(cfgs, steps=16, cands=cands)
+    assert best in cands
+    assert len(results) == len(cands) and all(sec > 0 for _, sec in results)
