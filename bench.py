@@ -102,6 +102,84 @@ def copy_probe(nbytes: int = 2 << 30, reps: int = 10):
     return {"bytes_each_way": nbytes, "reps": reps, "GBs": round(2 * nbytes / sec / 1e9, 1)}
 
 
+def run_batched(count: int = 512, steps: int = 2000, storage: str = "f32_shifted", loop_steps: int = 2000,
+                tune_steps: int = 64):
+    """The batched channel sweep: `count` uneven Couette / Poiseuille
+    instances (Nx = 4, Ny 32..1024, levels 2..6), `steps` steps each.
+
+    The schedule is autotuned on scratch lattices; the tuned batch is timed
+    over all `steps` steps; the plain per-solve loop (each instance alone,
+    one launch per step, one instance after the other on one stream) is
+    timed over `loop_steps` steps per instance on fresh lattices.  When the
+    step counts agree, every instance's populations are compared bitwise
+    between the two."""
+    import torch
+    from paper_1905_04597_amd import batching, glbm
+    from paper_1905_04597_amd import workloads as wl
+
+    ws = wl.sweep_workloads(count, steps=steps, storage=storage)
+    cfgs = [glbm.config_from_workload(w) for w in ws]
+    nodes = sum(w.nodes for w in ws)
+    pops = sum(w.nodes * w.nvel for w in ws)
+    t0 = time.perf_counter()
+    best, table = batching.autotune(cfgs, steps=tune_steps)
+    tune_s = time.perf_counter() - t0
+
+    batched = [glbm.Solver(c) for c in cfgs]
+    for s in batched:
+        s.init_fields()
+    torch.cuda.synchronize()
+    b = glbm.Batch(batched, **best)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    b.step(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    batch_s = start.elapsed_time(stop) / 1e3
+    b.close()
+
+    loop = [glbm.Solver(c) for c in cfgs]
+    for s in loop:
+        s.init_fields()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(count + 1)]
+    ev[0].record()
+    for i, s in enumerate(loop):
+        s.step(loop_steps)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    done = [ev[0].elapsed_time(e) / 1e3 for e in ev[1:]]
+    loop_s = done[-1]
+
+    equal = None
+    if loop_steps == steps:
+        equal = all(torch.equal(a.populations(), c.populations()) for a, c in zip(batched, loop))
+    for s in batched + loop:
+        s.close()
+    bytes_step = sum(2 * w.nodes * w.nvel * ELEM_BYTES[storage] for w in ws)
+    per_solve = loop_s / loop_steps * steps
+    done_sorted = sorted(d / loop_steps * steps for d in done)
+    return {
+        "workload": "%d Couette/Poiseuille channels, Nx=4, Ny~U{32..1024}, level~U{2..6}, log10 Kn~U[-3,1], "
+                    "speed~U[0.01,0.1] c_s, %d steps each, seed 190504597" % (count, steps),
+        "storage": storage, "instances": count, "nodes": nodes, "populations": pops,
+        "schedule": best, "autotune_s": round(tune_s, 2),
+        "autotune_us_per_step": {"%(tile_nodes)d/%(order)s/g%(graph_steps)d" % o: round(sec * 1e6, 1)
+                                 for o, sec in table},
+        "batched": {"solves_per_s": round(count / batch_s, 2), "seconds": round(batch_s, 4),
+                    "glups": round(nodes * steps / batch_s / 1e9, 3),
+                    "achieved_GBs": round(bytes_step * steps / batch_s / 1e9, 1),
+                    "latency_p50_s": round(batch_s, 4), "latency_p99_s": round(batch_s, 4)},
+        "per_solve_loop": {"solves_per_s": round(count / per_solve, 2), "seconds": round(per_solve, 4),
+                           "measured_steps": loop_steps,
+                           "glups": round(nodes * steps / per_solve / 1e9, 3),
+                           "latency_p50_s": round(done_sorted[len(done_sorted) // 2], 4),
+                           "latency_p99_s": round(done_sorted[min(count - 1, int(0.99 * count))], 4)},
+        "speedup": round(per_solve / batch_s, 2),
+        "bitwise_equal": equal,
+    }
+
+
 def cpu_baseline(level: int = 5, nx: int = 64, ny: int = 1024, steps: int = 40):
     """The FP64 oracle (single-threaded C) on a bounded sample of the workload:
     the same level, wall distance and parameters, a narrower channel."""
@@ -143,6 +221,11 @@ def main(argv=None):
     ap.add_argument("--sweep-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true", help="print only the batched sweep record")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-loop-steps", type=int, default=2000)
     a = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -154,6 +237,9 @@ def main(argv=None):
     import torch
 
     torch.cuda.set_device(0)
+    if a.batched_only:
+        print(json.dumps(run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)), flush=True)
+        return 0
     copy = copy_probe(reps=10 if not a.copy_probe else 20)
     main_run = run_gpu(a.level, a.nx, a.ny, a.storage, a.steps, a.warmup)
     sweep = None
@@ -164,6 +250,7 @@ def main(argv=None):
             sweep.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
                           if k in ("k", "Q", "glups", "achieved_GBs", "ms_per_step")})
             sweep[-1]["frac"] = round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)
+    batched = None if a.no_batched else run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.level)
     achieved = main_run["achieved_GBs"]
     line = {
@@ -201,6 +288,8 @@ def main(argv=None):
     }
     if sweep is not None:
         line["per_k"] = sweep
+    if batched is not None:
+        line["batched_sweep"] = batched
     print(json.dumps(line), flush=True)
     return 0
 

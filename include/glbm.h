@@ -104,7 +104,10 @@ typedef struct glbm_stats {
 typedef struct glbm_solver glbm_t;
 
 /* Bytes of ONE population buffer for cfg (the library's internal layout:
- * [q][y][x + halo] with ghost columns), or 0 if cfg is invalid.  The caller
+ * velocity planes [q][y][row], each plane rounded up to 256 bytes; a row is
+ * nx columns plus ghost columns padded to a multiple of 64, or exactly nx
+ * columns for two-dimensional lattices with periodic x and nx < 64), or 0 if
+ * cfg is invalid.  The caller
  * allocates two such buffers on the device (for HBM-budget admission this is
  * the whole device footprint apart from a few KB of tables). */
 size_t glbm_population_bytes(const glbm_config *cfg);

@@ -2,8 +2,9 @@
 
 Usage: python -m paper_1905_04597_amd.build [--jobs J] [--incremental]
 
-Every hierarchy level is compiled as its own object (they are the slow
-part), in parallel, and linked into ``paper_1905_04597_amd/libglbm.so``.
+Every hierarchy level and row layout is compiled as its own object (they
+are the slow part), in parallel, and linked into
+``paper_1905_04597_amd/libglbm.so``.
 """
 from __future__ import annotations
 
@@ -36,17 +37,18 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _deps():
-    return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))] + [
-        os.path.join(os.path.dirname(HERE), "include", "glbm.h")
-    ]
+def _deps(src: str):
+    common = [os.path.join(CSRC, f) for f in ("glbm_device.h", "glbm_internal.h")]
+    if src.endswith("glbm_api.hip"):
+        common.append(os.path.join(os.path.dirname(HERE), "include", "glbm.h"))
+    return [src] + common
 
 
-def _stale(obj: str) -> bool:
+def _stale(src: str, obj: str) -> bool:
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    return any(os.path.getmtime(d) > t for d in _deps())
+    return any(os.path.getmtime(d) > t for d in _deps(src))
 
 
 def _compile(args):
@@ -62,9 +64,11 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     os.makedirs(BUILD, exist_ok=True)
     tasks = [(os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), [])]
     for lv in LEVELS:
-        tasks.append((os.path.join(CSRC, "glbm_inst.hip"), os.path.join(BUILD, "glbm_inst_%d.o" % lv),
-                      ["-DGLBM_LEVEL=%d" % lv]))
-    todo = [t for t in tasks if not incremental or _stale(t[1])]
+        for compact in (0, 1):
+            tasks.append((os.path.join(CSRC, "glbm_inst.hip"),
+                          os.path.join(BUILD, "glbm_inst_%d%s.o" % (lv, "c" if compact else "")),
+                          ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_COMPACT=%d" % compact]))
+    todo = [t for t in tasks if not incremental or _stale(t[0], t[1])]
     jobs = jobs or min(len(todo) or 1, os.cpu_count() or 4, 16)
     if todo:
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

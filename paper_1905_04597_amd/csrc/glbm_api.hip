@@ -49,6 +49,14 @@ void register_all()
     register_level_6();
     register_level_7();
     register_mixed();
+    register_compact_1();
+    register_compact_2();
+    register_compact_3();
+    register_compact_4();
+    register_compact_5();
+    register_compact_6();
+    register_compact_7();
+    register_compact_mixed();
 }
 
 // Host copy of the per-axis equilibrium at rho = 1 (N-fold convolution of the
@@ -76,6 +84,7 @@ void host_axis_equilibrium(int N, double u, double *F)
 
 struct Geometry {
     int lx, ly, q, eb;
+    int bcx;  // kernel variant's x boundary and row layout (BcX)
     int64_t nx, ny, nxp;
     uint64_t plane_bytes, buf_bytes;
 };
@@ -110,8 +119,12 @@ int check_config(const glbm_config *c, Geometry *g)
     g->eb = (c->storage == GLBM_STORE_BF16_SHIFTED || c->storage == GLBM_STORE_BF16_SHIFTED_SR) ? 2 : 4;
     g->nx = nx;
     g->ny = ny;
-    g->nxp = (kGhost + nx + lx + 63) / 64 * 64;  // node x at column kGhost + x
-    g->plane_bytes = (uint64_t)(ny * g->nxp) * g->eb;
+    // periodic x narrower than a wave: compact rows of nx columns (node x at
+    // column x); otherwise padded rows with ghosts (node x at column kGhost + x)
+    const bool compact = c->dims == 2 && c->bc_x == GLBM_BC_PERIODIC && nx < kCompactBelow;
+    g->bcx = compact ? BCX_WRAP : c->bc_x == GLBM_BC_EQ_ENDS ? BCX_EQ : BCX_PERIODIC;
+    g->nxp = compact ? nx : (kGhost + nx + lx + 63) / 64 * 64;
+    g->plane_bytes = ((uint64_t)(ny * g->nxp) * g->eb + 255) & ~(uint64_t)255;
     g->buf_bytes = (g->plane_bytes * g->q + 255) & ~(uint64_t)255;
     if (nx * ny > (int64_t)0x7fffffff / 4) return fail(GLBM_ERR_INVALID, "too many nodes");
     if (g->buf_bytes >= ((uint64_t)1 << 32))
@@ -197,7 +210,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
 
     std::call_once(g_once, register_all);
     const int bcy = cfg->dims == 2 ? cfg->bc_y : GLBM_BC_PERIODIC;
-    const Variant *v = variant_slot(g.lx, g.ly, cfg->storage, cfg->bc_x, bcy);
+    const Variant *v = variant_slot(g.lx, g.ly, cfg->storage, g.bcx, bcy);
     if (!v->step)
         return fail(GLBM_ERR_UNSUPPORTED, "no kernels built for levels (%d, %d) with these boundaries", g.lx, g.ly);
 

@@ -18,6 +18,11 @@
 // an immediate offset.  With fixed equilibrium ends the ghosts hold the end
 // state and are never written.
 //
+// Narrow periodic lattices (nx below one wave) use a compact layout instead:
+// rows of exactly nx columns and no ghosts, so that a wave's 64 nodes are 64
+// consecutive values of each plane (several whole rows); the pull computes
+// the source column (x - c_x) mod nx once per velocity.
+//
 // Tables that depend only on the level (rest weights, half flux, force
 // shape) are compile-time constants folded into the instructions; tables
 // that depend on run-time parameters (wall emission at the wall speed) are
@@ -36,9 +41,13 @@ constexpr int kMaxQ1 = 2 * kMaxLevel + 1;
 constexpr int kBlock = 256;
 constexpr int kNumStats = 11;
 constexpr int kGhost = 64;  // padded column of node x = 0 (>= the largest level)
+constexpr int kCompactBelow = 64;  // periodic-x lattices narrower than this use compact rows
 
 enum StorageKind { ST_F32 = 0, ST_F32S = 1, ST_BF16S = 2, ST_BF16SR = 3 };
-enum BcX { BCX_PERIODIC = 0, BCX_EQ = 2 };
+// x boundary and row layout: periodic x with ghost columns (padded rows),
+// periodic x in the compact layout of narrow lattices (rows of exactly nx
+// columns, the pull wraps), fixed equilibrium ends (ghosts hold the ends).
+enum BcX { BCX_PERIODIC = 0, BCX_WRAP = 1, BCX_EQ = 2 };
 enum BcY { BCY_PERIODIC = 0, BCY_WALL = 1 };
 
 // ---------------------------------------------------------------- tables
@@ -328,6 +337,52 @@ struct Lat {
     static constexpr bool shifted = Elem<ST>::shifted;
 };
 
+// Byte offsets of the x sources of node x within a row (see the layouts
+// above).  Padded rows: the source of velocity index a (c_x = a - LX) is
+// column G + x - c_x, a constant shift that the load takes as an immediate.
+// Compact rows: column (x - c_x) mod nx, one register per velocity.
+template <int LX, int EB, int BCX>
+struct XAddr {
+    static constexpr int QX = 2 * LX + 1;
+    static constexpr bool compact = BCX == BCX_WRAP;
+    uint32_t col[compact ? QX : 1];
+    uint32_t self;
+    __device__ __forceinline__ XAddr(int x, int nx)
+    {
+        if constexpr (compact) {
+            unroll<QX>([&](auto A) {
+                constexpr int ca = (int)A - LX;
+                int c = x - ca;
+                if constexpr (ca > 0)
+                    while (c < 0) c += nx;
+                if constexpr (ca < 0)
+                    while (c >= nx) c -= nx;
+                col[A] = (uint32_t)c * (uint32_t)EB;
+            });
+            self = (uint32_t)x * (uint32_t)EB;
+        } else {
+            col[0] = (uint32_t)(x + kGhost - LX) * (uint32_t)EB;
+            self = (uint32_t)(x + kGhost) * (uint32_t)EB;
+        }
+    }
+    // source of velocity index a in the row that starts at byte rowb
+    template <int a>
+    __device__ __forceinline__ uint32_t src(uint32_t rowb) const
+    {
+        if constexpr (compact)
+            return rowb + col[a];
+        else
+            return rowb + col[0] + (uint32_t)((2 * LX - a) * EB);
+    }
+    __device__ __forceinline__ uint32_t own(uint32_t rowb) const { return rowb + self; }
+};
+
+template <int EB>
+__device__ __forceinline__ uint32_t row_bytes(const KArgs &p, int row)
+{
+    return (uint32_t)(row * p.nxp) * (uint32_t)EB;
+}
+
 // Mass absorbed by a diffuse wall in column x: the post-collision
 // populations that leave through the wall in this streaming and would land in
 // column x (sources at x - c_x in the rows within reach of the wall).  The
@@ -335,8 +390,9 @@ struct Lat {
 // unit-density equilibrium at the wall speed over the populations pointing
 // into the fluid, which conserves the mass of every column.  `mom` receives
 // the x momentum of the absorbed populations when requested.
-template <int LX, int LY, int ST, bool BOTTOM>
-__device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, int x, float *mom)
+template <int LX, int LY, int ST, int BCX, bool BOTTOM>
+__device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa,
+                                               float *mom)
 {
     using L = Lat<LX, LY, ST>;
     float s = 0.0f, m = 0.0f;
@@ -346,10 +402,10 @@ __device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, int x,
             constexpr int depth = cb < 0 ? -cb : cb;
             unroll<depth>([&](auto R) {
                 const int row = BOTTOM ? (int)R : p.ny - 1 - (int)R;
-                const uint32_t base = (uint32_t)(row * p.nxp + x + kGhost - LX) * (uint32_t)L::EB;
+                const uint32_t rowb = row_bytes<L::EB>(p, row);
                 unroll<L::QX>([&](auto A) {
                     constexpr int a = A, ca = a - LX;
-                    const float v = ld<ST>(rs, base + (LX - ca) * L::EB, (uint32_t)(b * L::QX + a) * p.plane_bytes);
+                    const float v = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)(b * L::QX + a) * p.plane_bytes);
                     s += v;
                     if (mom) m = __builtin_fmaf((float)ca, v, m);
                 });
@@ -363,16 +419,18 @@ __device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, int x,
 
 // Pre-collision populations of node (x, y) at the new time: pulled from the
 // source buffer, or emitted by a wall where the source row is outside.
-template <int LX, int LY, int ST, int BCY>
-__device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, int x, int y, float (&v)[2 * LY + 1][2 * LX + 1])
+template <int LX, int LY, int ST, int BCX, int BCY>
+__device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
+                                     float (&v)[2 * LY + 1][2 * LX + 1])
 {
     using L = Lat<LX, LY, ST>;
     float rw[2] = {0.0f, 0.0f};
     if constexpr (BCY == BCY_WALL) {
         // the mass the FP32 emission tables give out per unit wall density
         constexpr double jp = half_flux_f32<LY>();
-        if (y < LY) rw[0] = wall_absorbed<LX, LY, ST, true>(p, rs, x, nullptr) / (float)(jp * p.fwsum[0]);
-        if (y >= p.ny - LY) rw[1] = wall_absorbed<LX, LY, ST, false>(p, rs, x, nullptr) / (float)(jp * p.fwsum[1]);
+        if (y < LY) rw[0] = wall_absorbed<LX, LY, ST, BCX, true>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[0]);
+        if (y >= p.ny - LY)
+            rw[1] = wall_absorbed<LX, LY, ST, BCX, false>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[1]);
     }
     unroll<L::QY>([&](auto B) {
         constexpr int b = B, cb = b - LY;
@@ -396,10 +454,10 @@ __device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, int x, int y, fl
                     v[b][a] = rwb * p.fw[side][a];
             });
         } else {
-            const uint32_t base = (uint32_t)(ys * p.nxp + x + kGhost - LX) * (uint32_t)L::EB;
+            const uint32_t rowb = row_bytes<L::EB>(p, ys);
             unroll<L::QX>([&](auto A) {
-                constexpr int a = A, ca = a - LX;
-                v[b][a] = ld<ST>(rs, base + (LX - ca) * L::EB, (uint32_t)(b * L::QX + a) * p.plane_bytes);
+                constexpr int a = A;
+                v[b][a] = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)(b * L::QX + a) * p.plane_bytes);
             });
         }
     });
@@ -545,9 +603,10 @@ __device__ __forceinline__ void store_node(const KArgs &p, rsrc_t rd, int x, int
                                            const float (&v)[2 * LY + 1][2 * LX + 1], uint32_t h)
 {
     using L = Lat<LX, LY, ST>;
-    // columns holding node x: its own, and with periodic x every column of
-    // [G - LX, G + nx + LX) congruent to it modulo nx
+    // columns holding node x: its own, and with periodic padded rows every
+    // column of [G - LX, G + nx + LX) congruent to it modulo nx
     int pc = x + kGhost;
+    if constexpr (BCX == BCX_WRAP) pc = x;
     if constexpr (BCX == BCX_PERIODIC) pc = kGhost - LX + (x + LX) % p.nx;
     for (; pc < kGhost + p.nx + LX; pc += p.nx) {
         const uint32_t off = (uint32_t)(y * p.nxp + pc) * (uint32_t)L::EB;
@@ -589,6 +648,7 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
 {
     using L = Lat<LX, LY, ST>;
     using P = PackedRegs<LX, LY, ST>;
+    const XAddr<LX, 2, BCX> xa(x, p.nx);
     uint32_t pk[P::NP];
     unroll<L::QY>([&](auto B) {
         constexpr int b = B, cb = b - LY;
@@ -597,11 +657,11 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
             if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
             if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
         }
-        const uint32_t base = (uint32_t)(ys * p.nxp + x + kGhost - LX) * 2u;
+        const uint32_t rowb = row_bytes<2>(p, ys);
         unroll<L::QX>([&](auto A) {
-            constexpr int a = A, ca = a - LX, q = b * L::QX + a;
+            constexpr int a = A, q = b * L::QX + a;
             const uint32_t raw = (uint32_t)__builtin_bit_cast(
-                unsigned short, __builtin_amdgcn_raw_buffer_load_b16(rs, base + (LX - ca) * 2, (uint32_t)q * p.plane_bytes, 0));
+                unsigned short, __builtin_amdgcn_raw_buffer_load_b16(rs, xa.template src<a>(rowb), (uint32_t)q * p.plane_bytes, 0));
             if constexpr ((q & 1) == 0)
                 pk[q >> 1] = raw;
             else
@@ -613,6 +673,7 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
     density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
     collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
     int pc = x + kGhost;
+    if constexpr (BCX == BCX_WRAP) pc = x;
     if constexpr (BCX == BCX_PERIODIC) pc = kGhost - LX + (x + LX) % p.nx;
     for (; pc < kGhost + p.nx + LX; pc += p.nx) {
         const uint32_t off = (uint32_t)(y * p.nxp + pc) * 2u;
@@ -647,7 +708,8 @@ __device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
         step_packed<LX, LY, ST, BCX, BCY>(p, rs, rd, x, y, h);
     } else {
         float v[L::QY][L::QX];
-        pull<LX, LY, ST, BCY>(p, rs, x, y, v);
+        const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+        pull<LX, LY, ST, BCX, BCY>(p, rs, xa, y, v);
         FloatRegs<LX, LY> regs{v};
         float rho, jx, jy, ux, uy;
         density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
@@ -718,8 +780,9 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(KArgs p)
     const int y = i / p.nx, x = i - y * p.nx;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     float v[L::QY][L::QX];
+    const XAddr<LX, L::EB, BCX> xa(x, p.nx);
     if (p.local) {
-        const uint32_t base = (uint32_t)(y * p.nxp + x + kGhost) * (uint32_t)L::EB;
+        const uint32_t base = xa.own(row_bytes<L::EB>(p, y));
         unroll<L::QY>([&](auto B) {
             unroll<L::QX>([&](auto A) {
                 constexpr int a = A, b = B;
@@ -727,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(KArgs p)
             });
         });
     } else {
-        pull<LX, LY, ST, BCY>(p, rs, x, y, v);
+        pull<LX, LY, ST, BCX, BCY>(p, rs, xa, y, v);
     }
     double r = 0.0, jx = 0.0, jy = 0.0;
     unroll<L::QY>([&](auto B) {
@@ -877,7 +940,7 @@ __global__ __launch_bounds__(kBlock) void ends_kernel(KArgs p, float rho_left, f
 // [0] mass  [1] momentum x  [2] momentum y  [3] energy (post)  [4] sum u_x^2
 // [5] sum (u_x(t) - u_x(t-1))^2  [6] bottom absorbed mass  [7] bottom x momentum
 // [8] top absorbed mass  [9] top x momentum  [10] non-positive nodes
-template <int LX, int LY, int ST, int BCY>
+template <int LX, int LY, int ST, int BCX, int BCY>
 __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
 {
     using L = Lat<LX, LY, ST>;
@@ -887,7 +950,8 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
     if (i < p.nodes) {
         const int y = i / p.nx, x = i - y * p.nx;
         const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
-        const uint32_t base = (uint32_t)(y * p.nxp + x + kGhost) * (uint32_t)L::EB;
+        const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+        const uint32_t base = xa.own(row_bytes<L::EB>(p, y));
         double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
         unroll<L::QY>([&](auto B) {
             unroll<L::QX>([&](auto A) {
@@ -932,13 +996,13 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
         if constexpr (BCY == BCY_WALL) {
             if (y == 0) {
                 float m;
-                const float A = wall_absorbed<LX, LY, ST, true>(p, rs, x, &m);
+                const float A = wall_absorbed<LX, LY, ST, BCX, true>(p, rs, xa, &m);
                 acc[6] = A;
                 acc[7] = (double)m - (double)A * p.uw[0];
             }
             if (y == p.ny - 1) {
                 float m;
-                const float A = wall_absorbed<LX, LY, ST, false>(p, rs, x, &m);
+                const float A = wall_absorbed<LX, LY, ST, BCX, false>(p, rs, xa, &m);
                 acc[8] = A;
                 acc[9] = (double)m - (double)A * p.uw[1];
             }

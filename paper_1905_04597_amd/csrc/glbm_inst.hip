@@ -1,6 +1,8 @@
 // Kernel instantiations for one hierarchy level, selected at compile time
 // with -DGLBM_LEVEL=N (N = 1..7); -DGLBM_LEVEL=0 builds the mixed-level
-// lattices.  Each level is its own object file so the build runs in parallel.
+// lattices.  -DGLBM_COMPACT=1 builds the compact-row variants of the 2D
+// periodic-x lattices instead (narrow lattices).  Each (level, layout) is its
+// own object file so the build runs in parallel.
 #include "glbm_internal.h"
 
 namespace glbm {
@@ -35,7 +37,7 @@ struct Launchers {
     }
     static hipError_t stats(const KArgs &a, int grid, hipStream_t s)
     {
-        hipLaunchKernelGGL((stats_kernel<LX, LY, ST, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((stats_kernel<LX, LY, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
     static hipError_t ends(const KArgs &a, int grid, float rl, float rr, hipStream_t s)
@@ -81,9 +83,31 @@ void add_all_storages()
 
 }  // namespace
 
-#if GLBM_LEVEL >= 1
 #define GLBM_CAT2(a, b) a##b
 #define GLBM_CAT(a, b) GLBM_CAT2(a, b)
+
+#if GLBM_COMPACT
+// Two dimensions with periodic x in compact rows: the same lattices as the
+// padded 2D variants below.
+#if GLBM_LEVEL >= 1
+void GLBM_CAT(register_compact_, GLBM_LEVEL)()
+{
+    constexpr int N = GLBM_LEVEL;
+    add_all_storages<N, N, BCX_WRAP, BCY_PERIODIC>();
+    add_all_storages<N, N, BCX_WRAP, BCY_WALL>();
+}
+#else
+void register_compact_mixed()
+{
+    add_all_storages<1, 2, BCX_WRAP, BCY_WALL>();
+    add_all_storages<1, 3, BCX_WRAP, BCY_WALL>();
+    add_all_storages<1, 4, BCX_WRAP, BCY_WALL>();
+    add_all_storages<1, 5, BCX_WRAP, BCY_WALL>();
+    add_all_storages<1, 6, BCX_WRAP, BCY_WALL>();
+    add_all_storages<1, 7, BCX_WRAP, BCY_WALL>();
+}
+#endif
+#elif GLBM_LEVEL >= 1
 void GLBM_CAT(register_level_, GLBM_LEVEL)()
 {
     constexpr int N = GLBM_LEVEL;

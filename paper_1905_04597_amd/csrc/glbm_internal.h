@@ -38,5 +38,13 @@ void register_level_5();
 void register_level_6();
 void register_level_7();
 void register_mixed();
+void register_compact_1();
+void register_compact_2();
+void register_compact_3();
+void register_compact_4();
+void register_compact_5();
+void register_compact_6();
+void register_compact_7();
+void register_compact_mixed();
 
 }  // namespace glbm

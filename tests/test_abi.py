@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_population_bytes_layout():
     # [q][y][nxp], nxp = 64 + nx + N rounded up to a multiple of 64 columns,
-    # times the element size of the storage, rounded to 256 bytes
+    # times the element size of the storage, each plane rounded to 256 bytes
     def nxp(nx, N):
         return (64 + nx + N + 63) // 64 * 64
     c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="f32")
@@ -49,6 +49,14 @@ def test_population_bytes_layout():
     assert glbm.population_bytes(c) == ((121 * 1024 * nxp(4096, 5) * 2 + 255) // 256) * 256
     c = glbm.make_config(1, 3, 0, 2000, 1, kn=0.01, bc_x="eq_ends")
     assert glbm.population_bytes(c) == ((7 * nxp(2000, 3) * 4 + 255) // 256) * 256
+    # two dimensions, periodic x narrower than 64: compact rows of nx columns,
+    # each plane rounded up to 256 bytes
+    c = glbm.make_config(2, 3, 3, 4, 37, kn=0.1, bc_y="wall", storage="f32_shifted")
+    assert glbm.population_bytes(c) == 49 * ((37 * 4 * 4 + 255) // 256 * 256)
+    c = glbm.make_config(2, 6, 6, 63, 100, tau=0.8, storage="bf16_shifted_sr")
+    assert glbm.population_bytes(c) == 169 * ((100 * 63 * 2 + 255) // 256 * 256)
+    c = glbm.make_config(2, 6, 6, 64, 100, tau=0.8, storage="bf16_shifted_sr")
+    assert glbm.population_bytes(c) == 169 * 100 * nxp(64, 6) * 2
 
 
 @pytest.mark.parametrize("kwargs,needle", [

@@ -5,7 +5,10 @@ Each case runs the same seeded inputs through both and compares the moments
 relative error max|q - q_ref| / max|q_ref| (floors in tests/gpu_common.py):
 1e-5 for FP32 storage, 1e-3 for BF16 storage.  Sizes span several 256-node
 tiles with a ragged tail, plus the degenerate shapes (nx below the level, so
-that ghost columns wrap several times; nx = 3 or 4 channels; 1D).
+that ghost columns or the pull wrap several times; nx = 3 or 4 channels;
+1D).  Two-dimensional lattices with periodic x and nx < 64 run in compact
+rows (no ghosts, the pull wraps), the others in padded rows: both layouts
+are covered, and x-uniform channels are compared bitwise across them.
 
 Which storage meets which bound (tests/gpu_common.py BOUND): FP32 deviation
 storage (f - S, the FP32 path) meets 1e-5 on every case.  Plain FP32 keeps
@@ -54,6 +57,8 @@ CASES = {
                                      wall_u=(-0.04, 0.04)), "fields", 5, F32),
     "mixed_d1q3xd1q7_walls": (dict(dims=2, level_x=1, level_y=3, nx=5, ny=40, tau=0.9, bc_y="wall",
                                    wall_u=(-0.05, 0.05), g=1e-4), "wave", 50, F32),
+    "d2q49_nx2_wrap": (dict(dims=2, level_x=3, level_y=3, nx=2, ny=9, tau=0.9, g=1e-4), "populations", 20, F32),
+    "d2q81_periodic_wave_nx16": (dict(dims=2, level_x=4, level_y=4, nx=16, ny=40, tau=1.5), "wave", 100, ALL),
 }
 
 PARAMS = [(name, st) for name, (_, _, _, sts) in CASES.items() for st in sts]
@@ -96,16 +101,45 @@ def test_parity_with_oracle(name, storage):
     assert sg["nonpositive_nodes"] == so["nonpositive_nodes"]
 
 
-def test_free_streaming_permutation_bitwise():
+@pytest.mark.parametrize("nx,ny", [(5, 6), (66, 6)], ids=["compact_rows", "padded_rows"])
+def test_free_streaming_permutation_bitwise(nx, ny):
     """tau = 1e30 gives omega = 1e-30: the relaxation term rounds away and a
     step is a pure permutation, so the state returns bitwise after lcm(nx, ny)."""
     from paper_1905_04597_amd import glbm
 
-    cfg = glbm.make_config(2, 3, 3, 5, 6, tau=1e30)
+    period = nx * ny // math.gcd(nx, ny)
+    cfg = glbm.make_config(2, 3, 3, nx, ny, tau=1e30)
     gpu = glbm.Solver(cfg)
-    f0 = wl.random_populations(3, 49, 5, 6)
+    f0 = wl.random_populations(3, 49, nx, ny)
     gpu.init_populations(f0)
-    gpu.step(29)
+    gpu.step(period - 1)
     assert not np.array_equal(gpu.populations().cpu().numpy(), f0)
     gpu.step(1)
     assert np.array_equal(gpu.populations().cpu().numpy(), f0)
+
+
+@pytest.mark.parametrize("storage", ["f32_shifted", "f32"])
+@pytest.mark.parametrize("level", [2, 5])
+def test_compact_rows_match_padded_rows_bitwise(level, storage):
+    """An x-uniform channel (fields varying across y only) evolves the same in
+    every column whatever the width, and a node's arithmetic does not depend
+    on the row layout: the columns of a 4-wide lattice (compact rows) equal
+    those of a 64-wide one (padded rows) bitwise."""
+    from paper_1905_04597_amd import glbm
+
+    ny = 40
+    y = (np.arange(ny) + 0.5) / ny
+    prof = {"rho": 1 + 0.02 * np.cos(2 * np.pi * y), "ux": 0.04 * np.sin(2 * np.pi * y),
+            "uy": 0.01 * np.cos(4 * np.pi * y)}
+    cols = []
+    for nx in (4, 64):
+        cfg = glbm.make_config(2, level, level, nx, ny, kn=0.2, bc_y="wall", wall_u=(-0.03, 0.05), g=2e-5,
+                               storage=storage)
+        s = glbm.Solver(cfg)
+        f = {k: np.repeat(v.astype(np.float32)[:, None], nx, axis=1) for k, v in prof.items()}
+        s.init_fields(f["rho"], f["ux"], f["uy"])
+        s.step(30)
+        cols.append(s.populations().cpu().numpy())
+    narrow, wide = cols
+    for x in range(64):
+        assert np.array_equal(wide[:, :, x], narrow[:, :, x % 4]), x
