@@ -2,17 +2,21 @@
 
 Workload (default): force-driven Poiseuille channel, tensor-product
 G-D2Q(11x11) (level N = 5 per axis, k = 4, 121 velocities), 4096 x 1024
-nodes, diffuse walls at rest, g = 1e-5, Kn = 0.1, FP32 populations; inputs are
+nodes, diffuse walls at rest, g = 1e-5, Kn = 0.1, FP32 populations stored as
+deviations from the rest state (the FP32 path that meets 1e-5); inputs are
 resident in HBM before the timed region.  One "step" is one time step of the
 whole lattice (one launch of the fused kernel).
 
 Prints ONE JSON line: GLUPS (1e9 node updates per second), the roofline of
 the step kernel (algorithmic bytes 2 Q s per node update over the average
-launch duration, against the 8 TB/s HBM peak), an optional per-level sweep and
+launch duration, against the 8 TB/s HBM peak), a per-level sweep, the batched
+channel sweep (512 uneven instances, batched vs the per-solve loop), the
+served mix (continuous batching vs the per-solve loop, p50/p99 latency) and
 the FP64 oracle timed on the host cores over a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--storage f32|bf16_shifted_sr|...]
-                    [--no-sweep] [--no-cpu-baseline] [--copy-probe]
+    python bench.py [--steps K] [--warmup W] [--storage f32_shifted|bf16_shifted_sr|...]
+                    [--no-sweep] [--no-batched] [--no-served] [--no-cpu-baseline]
+                    [--batched-only] [--served-only]
 """
 from __future__ import annotations
 
@@ -180,6 +184,51 @@ def run_batched(count: int = 512, steps: int = 2000, storage: str = "f32_shifted
     }
 
 
+def _same_moments(a, b) -> bool:
+    import torch
+
+    return all(bool(((a[k] == b[k]) | (torch.isnan(a[k]) & torch.isnan(b[k]))).all())
+               for k in ("rho", "ux", "uy", "T", "pxy"))
+
+
+def run_served(duration: float = 12.0, warm: float = 2.0, sample: int = 16, loop_max: float = 90.0):
+    """The served mix: Poisson arrivals at 200 requests/s (seeds 1905 / 4597)
+    of Sod, Couette and Poiseuille solves, served by the continuous-batching
+    server within a 200 GB budget; requests arriving in [warm, duration) are
+    measured.  Then the plain per-solve loop serves the same arrivals.  A
+    spread of `sample` requests is re-run alone and compared bitwise."""
+    import numpy as np
+    import torch
+    from paper_1905_04597_amd import serving
+    from paper_1905_04597_amd import workloads as wl
+
+    arrivals = wl.served_requests(duration=duration)
+    ids = set(int(i) for i in np.linspace(0, len(arrivals) - 1, sample))
+    srv = serving.Server(keep_results=ids)
+    t0 = time.perf_counter()
+    reqs = srv.run(arrivals, max_seconds=duration + 60)
+    served_wall = time.perf_counter() - t0
+    summ = serving.summarize(reqs, (warm, duration))
+    torch.cuda.synchronize()
+    equal = all(_same_moments(r.result, serving.solve_alone(r.workload, r.steps)) for r in reqs if r.rid in ids)
+    for r in reqs:
+        r.result = None
+    loop = serving.serve_per_solve(arrivals, max_seconds=loop_max)
+    lsum = serving.summarize(loop, (warm, duration))
+    eb = serving.ELEM_BYTES
+    offered = sum(serving.step_bytes(w) * w.steps for _, w in arrivals) / duration
+    return {
+        "workload": "Poisson arrivals 200/s for %.0f s (first %.0f s warm-up), Sod (500..20000 nodes, 1000 steps) / "
+                    "Couette / Poiseuille (Ny 32..2048, Nx 4..2048, 200 steps), level 1..7, log10 Kn U[-3,1], "
+                    "FP32 or BF16 deviation storage, budget 200 GB, seeds 1905/4597" % (duration, warm),
+        "offered_GBs": round(offered / 1e9, 1),
+        "server": dict(summ, wall_s=round(served_wall, 2), peak_population_GB=round(srv.peak_in_use / 1e9, 2),
+                       chunks=[l.chunks for l in srv.lanes]),
+        "per_solve_loop": lsum,
+        "alone_vs_mix_bitwise": equal, "alone_vs_mix_sample": len(ids),
+    }
+
+
 def cpu_baseline(level: int = 5, nx: int = 64, ny: int = 1024, steps: int = 40):
     """The FP64 oracle (single-threaded C) on a bounded sample of the workload:
     the same level, wall distance and parameters, a narrower channel."""
@@ -213,7 +262,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--storage", default="f32", choices=sorted(ELEM_BYTES))
+    ap.add_argument("--storage", default="f32_shifted", choices=sorted(ELEM_BYTES))
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--nx", type=int, default=4096)
     ap.add_argument("--ny", type=int, default=1024)
@@ -226,6 +275,9 @@ def main(argv=None):
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-loop-steps", type=int, default=2000)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-only", action="store_true", help="print only the served-mix record")
+    ap.add_argument("--served-seconds", type=float, default=12.0)
     a = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -237,6 +289,9 @@ def main(argv=None):
     import torch
 
     torch.cuda.set_device(0)
+    if a.served_only:
+        print(json.dumps(run_served(a.served_seconds)), flush=True)
+        return 0
     if a.batched_only:
         print(json.dumps(run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)), flush=True)
         return 0
@@ -251,6 +306,7 @@ def main(argv=None):
                           if k in ("k", "Q", "glups", "achieved_GBs", "ms_per_step")})
             sweep[-1]["frac"] = round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)
     batched = None if a.no_batched else run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)
+    served = None if a.no_served else run_served(a.served_seconds)
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.level)
     achieved = main_run["achieved_GBs"]
     line = {
@@ -290,6 +346,8 @@ def main(argv=None):
         line["per_k"] = sweep
     if batched is not None:
         line["batched_sweep"] = batched
+    if served is not None:
+        line["served_mix"] = served
     print(json.dumps(line), flush=True)
     return 0
 

@@ -143,15 +143,18 @@ int glbm_moments(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *p
 /* Copy f(t) (pre-collision, FP32, canonical [Q][ny][nx]) into device memory. */
 int glbm_get_populations(glbm_t *h, float *out);
 
-/* Global FP64 diagnostics at the current time.  Synchronizes the stream. */
+/* Global FP64 diagnostics at the current time.  Synchronizes the stream.  The
+ * first call allocates the solver's small FP64 reduction buffers. */
 int glbm_stats(glbm_t *h, glbm_stats_t *out);
 
 /* Derived parameters: relaxation time, collision frequency 1/(tau + 1/2),
  * number of velocities, current time.  Host pointers; any may be NULL. */
 int glbm_info(const glbm_t *h, double *tau, double *omega, int32_t *nvel, int64_t *time);
 
-/* Release the handle (host state and the library's small device tables).
- * Caller-owned buffers are not touched.  Waits for the handle's stream. */
+/* Release the handle (host state, and the FP64 reduction buffers if
+ * glbm_stats allocated them: then it first waits for the handle's stream).
+ * Caller-owned buffers are not touched: keep them until the work enqueued on
+ * them has run. */
 int glbm_destroy(glbm_t *h);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -164,7 +167,9 @@ const char *glbm_last_error(void);
  * run of nodes of one member; a chunk of steps is captured once into a HIP
  * graph and replayed.  Every node runs exactly the code of glbm_step, so a
  * member's populations are bitwise those of the member stepped alone
- * (stochastic-rounding seeds included).
+ * (stochastic-rounding seeds included).  The batch's device tables (a few
+ * hundred bytes per member and per tile) are one allocation of the library,
+ * uploaded from a pinned host copy.
  * ------------------------------------------------------------------------ */
 #define GLBM_ORDER_MEMBER 0        /* tiles of each member contiguous */
 #define GLBM_ORDER_INTERLEAVE 1    /* tiles dealt round-robin over the members */
@@ -183,13 +188,24 @@ typedef struct glbm_batch glbm_batch_t;
  * the default stream, joined through events).  While a solver belongs to a
  * batch, glbm_step on it returns GLBM_ERR_STATE; glbm_moments, glbm_stats and
  * glbm_get_populations keep working (on the solver's own stream: synchronise
- * the two streams if they differ).  opt may be NULL (defaults).  Small device
- * tables are allocated here and released by glbm_batch_destroy. */
+ * the two streams if they differ).  opt may be NULL (defaults).  The tables
+ * are allocated here and released by glbm_batch_destroy. */
 int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_options *opt, void *stream,
                       glbm_batch_t **out);
 
 /* Advance every member by nsteps >= 0 steps. */
 int glbm_batch_step(glbm_batch_t *b, int64_t nsteps);
+
+/* Replace the member set (continuous batching: solvers join and leave between
+ * steps).  Same rules as glbm_batch_create, except that n may be 0 (an empty
+ * batch steps as a no-op and keeps its tables); members of this batch may stay,
+ * members left out are released (they may be stepped alone again once the
+ * batch's stream has run the work enqueued so far).  The tables are
+ * re-planned in place and uploaded on the batch's stream, so work already
+ * enqueued runs with the old plan; device memory is allocated only when the
+ * new plan is larger than any before.  On failure the old members stay in the
+ * batch but it cannot step until an update succeeds. */
+int glbm_batch_update(glbm_batch_t *b, glbm_t *const *members, int32_t n);
 
 /* Release the batch (members stay valid and can be stepped alone again).
  * Waits for the batch's work. */

@@ -260,15 +260,8 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
         a.uw[side] = (float)U;
     }
 
-    hipError_t e = hipMalloc((void **)&h->d_partials, sizeof(double) * kNumStats * (size_t)h->grid);
-    if (e == hipSuccess) e = hipMalloc((void **)&h->d_out, sizeof(double) * kNumStats);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_out, sizeof(double) * kNumStats, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        (void)hipFree(h->d_partials);
-        (void)hipFree(h->d_out);
-        delete h;
-        return hip_fail(e, "allocating statistics buffers");
-    }
+    // the FP64 statistics buffers are allocated by the first glbm_stats call,
+    // so that a solver that never asks for them costs no device allocation
     *out = h;
     return GLBM_OK;
 }
@@ -365,11 +358,25 @@ int glbm_stats(glbm_t *h, glbm_stats_t *out)
 {
     if (!h || !out) return fail(GLBM_ERR_INVALID, "NULL argument");
     if (!h->ready) return fail(GLBM_ERR_STATE, "stats before init");
+    hipError_t e = hipSuccess;
+    if (!h->d_partials) {
+        e = hipMalloc((void **)&h->d_partials, sizeof(double) * kNumStats * (size_t)h->grid);
+        if (e == hipSuccess) e = hipMalloc((void **)&h->d_out, sizeof(double) * kNumStats);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_out, sizeof(double) * kNumStats, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipFree(h->d_partials);
+            (void)hipFree(h->d_out);
+            h->d_partials = nullptr;
+            h->d_out = nullptr;
+            h->h_out = nullptr;
+            return hip_fail(e, "allocating statistics buffers");
+        }
+    }
     KArgs a = h->base;
     a.src = h->buf[h->cur];
     a.prev = h->t > 0 ? h->buf[1 - h->cur] : nullptr;
     a.partials = h->d_partials;
-    hipError_t e = h->var->stats(a, h->grid, h->stream);
+    e = h->var->stats(a, h->grid, h->stream);
     if (e != hipSuccess) return hip_fail(e, "launching the stats kernel");
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kBlock), 0, h->stream, h->d_partials, h->grid, h->d_out);
     e = hipGetLastError();
@@ -406,10 +413,13 @@ int glbm_destroy(glbm_t *h)
 {
     if (!h) return GLBM_OK;
     if (h->in_batch) return fail(GLBM_ERR_STATE, "the solver belongs to a batch: destroy the batch first");
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(h->d_partials);
-    (void)hipFree(h->d_out);
-    (void)hipHostFree(h->h_out);
+    if (h->d_partials) {
+        // statistics kernels may still use these buffers
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->d_partials);
+        (void)hipFree(h->d_out);
+        (void)hipHostFree(h->h_out);
+    }
     delete h;
     return GLBM_OK;
 }
@@ -418,37 +428,51 @@ int glbm_destroy(glbm_t *h)
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches
+//
+// All device tables of a batch live in one allocation, uploaded from a
+// pinned host copy with one asynchronous copy on the batch's stream:
+//   [step counter int64][phase int32 x n][t0 int64 x n][args KArgs x 2n][tiles]
+// Re-planning (glbm_batch_update) rewrites them in place; the allocation
+// grows (by doubling) only when a plan does not fit.
 
 struct glbm_batch {
     struct RowSet {
         const Variant *var;
-        int rows;            // StepRows
-        BatchTile *d_tiles;  // device tile table
+        int rows;        // StepRows
+        size_t tiles;    // byte offset of the set's tiles in the table block
         int ntiles;
     };
+    glbm_batch_options opt;
     std::vector<glbm_solver *> members;
     std::vector<RowSet> sets;
-    hipStream_t user;     // caller's stream (may be NULL)
-    hipStream_t exec;     // stream the batch launches on
+    hipStream_t user;  // caller's stream (may be NULL)
+    hipStream_t exec;  // stream the batch launches on
     bool own_stream;
-    hipEvent_t ev_in, ev_out;
-    KArgs *d_args;
-    int32_t *d_phase;
-    int64_t *d_t0, *d_bstep;
-    int block, graph_k;
+    hipEvent_t ev_in, ev_out, ev_staged;
+    char *d_mem, *h_mem;  // device tables and their pinned host copy
+    size_t cap;           // bytes of each
+    size_t o_phase, o_t0, o_args;
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
+    bool planned;  // the tables match `members`
 };
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static void release_graph(glbm_batch *b)
+{
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+}
 
 static void batch_free(glbm_batch *b)
 {
-    for (auto &r : b->sets) (void)hipFree(r.d_tiles);
-    (void)hipFree(b->d_args);
-    (void)hipFree(b->d_phase);
-    (void)hipFree(b->d_t0);
-    (void)hipFree(b->d_bstep);
-    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    release_graph(b);
+    (void)hipFree(b->d_mem);
+    (void)hipHostFree(b->h_mem);
+    if (b->ev_staged) (void)hipEventDestroy(b->ev_staged);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->own_stream) (void)hipStreamDestroy(b->exec);
@@ -456,18 +480,179 @@ static void batch_free(glbm_batch *b)
     delete b;
 }
 
+template <class T>
+static T *at(char *base, size_t off)
+{
+    return reinterpret_cast<T *>(base + off);
+}
+
 // One chunk of k steps: launches l = 0..k-1 of every row set, then the device
 // step counter advances by k.
 static hipError_t batch_chunk(glbm_batch *b, int k)
 {
+    int64_t *bstep = at<int64_t>(b->d_mem, 0);
+    const int32_t *phase = at<int32_t>(b->d_mem, b->o_phase);
+    const int64_t *t0 = at<int64_t>(b->d_mem, b->o_t0);
+    const KArgs *args = at<KArgs>(b->d_mem, b->o_args);
     for (int l = 0; l < k; ++l)
         for (auto &r : b->sets) {
-            hipError_t e = r.var->batch(r.rows, r.d_tiles, r.ntiles, b->block, b->d_args, b->d_phase, b->d_t0,
-                                        b->d_bstep, l, b->exec);
+            hipError_t e = r.var->batch(r.rows, at<BatchTile>(b->d_mem, r.tiles), r.ntiles, b->opt.tile_nodes, args,
+                                        phase, t0, bstep, l, b->exec);
             if (e != hipSuccess) return e;
         }
-    hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->exec, b->d_bstep, (int64_t)k);
+    hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->exec, bstep, (int64_t)k);
     return hipGetLastError();
+}
+
+// Check a prospective member list (members of `self` may stay; an update may
+// empty the batch).
+static int check_members(glbm_t *const *members, int32_t n, const glbm_batch *self)
+{
+    if (self ? (n < 0 || (n > 0 && !members)) : (!members || n < 1))
+        return fail(GLBM_ERR_INVALID, "a batch needs at least one member");
+    for (int i = 0; i < n; ++i) {
+        glbm_solver *m = members[i];
+        if (!m) return fail(GLBM_ERR_INVALID, "member %d is NULL", i);
+        if (!m->ready) return fail(GLBM_ERR_STATE, "member %d is not initialised", i);
+        const bool mine = self && std::find(self->members.begin(), self->members.end(), m) != self->members.end();
+        if (m->in_batch && !mine) return fail(GLBM_ERR_STATE, "member %d already belongs to a batch", i);
+        for (int j = 0; j < i; ++j)
+            if (members[j] == m) return fail(GLBM_ERR_INVALID, "member %d appears twice", i);
+    }
+    return GLBM_OK;
+}
+
+// Lay out the tables for `members` in the pinned host copy (growing both
+// copies if needed), upload them on the batch's stream and re-capture the
+// graph.  On failure the batch is left without a valid plan.
+static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
+{
+    b->planned = false;
+    struct Part {
+        int member, count;
+        double work;
+    };
+    const int tile = b->opt.tile_nodes;
+    std::vector<const Variant *> vars;
+    for (int i = 0; i < n; ++i)
+        if (std::find(vars.begin(), vars.end(), members[i]->var) == vars.end()) vars.push_back(members[i]->var);
+    // tile lists per (variant, row set)
+    std::vector<glbm_batch::RowSet> sets;
+    std::vector<std::vector<BatchTile>> lists;
+    for (const Variant *v : vars) {
+        const int rowsets[2][2] = {{ROWS_INTERIOR, ROWS_WALLS}, {ROWS_ALL, -1}};
+        for (int rsi = 0; rsi < 2; ++rsi) {
+            const int rows = rowsets[v->split_rows ? 0 : 1][rsi];
+            if (rows < 0) break;
+            std::vector<Part> parts;
+            for (int i = 0; i < n; ++i) {
+                const glbm_solver *m = members[i];
+                if (m->var != v) continue;
+                const int64_t nx = m->geo.nx, ny = m->geo.ny, ly = m->geo.ly;
+                const int64_t cnt = rows == ROWS_ALL ? nx * ny : rows == ROWS_INTERIOR ? (ny - 2 * ly) * nx : 2 * ly * nx;
+                if (cnt > 0) parts.push_back({i, (int)cnt, (double)cnt * m->geo.q});
+            }
+            if (b->opt.order == GLBM_ORDER_LARGEST_FIRST)
+                std::stable_sort(parts.begin(), parts.end(), [](const Part &x, const Part &y) { return x.work > y.work; });
+            std::vector<BatchTile> tiles;
+            if (b->opt.order == GLBM_ORDER_INTERLEAVE) {
+                for (int first = 0;; first += tile) {
+                    bool any = false;
+                    for (const Part &pt : parts)
+                        if (first < pt.count) {
+                            tiles.push_back({pt.member, first, std::min(tile, pt.count - first), 0});
+                            any = true;
+                        }
+                    if (!any) break;
+                }
+            } else {
+                for (const Part &pt : parts)
+                    for (int first = 0; first < pt.count; first += tile)
+                        tiles.push_back({pt.member, first, std::min(tile, pt.count - first), 0});
+            }
+            if (tiles.empty()) continue;
+            sets.push_back({v, rows, 0, (int)tiles.size()});
+            lists.push_back(std::move(tiles));
+        }
+    }
+    // layout
+    size_t off = 256;
+    b->o_phase = off;
+    off = align_up(off + sizeof(int32_t) * n, 256);
+    b->o_t0 = off;
+    off = align_up(off + sizeof(int64_t) * n, 256);
+    b->o_args = off;
+    off = align_up(off + sizeof(KArgs) * 2 * (size_t)n, 256);
+    for (size_t k = 0; k < sets.size(); ++k) {
+        sets[k].tiles = off;
+        off = align_up(off + sizeof(BatchTile) * lists[k].size(), 256);
+    }
+    const size_t need = off;
+    b->sets.clear();
+    release_graph(b);
+
+    // the previous upload must have left the pinned copy before it is rewritten
+    hipError_t e = hipEventSynchronize(b->ev_staged);
+    if (e == hipSuccess && need > b->cap) {
+        size_t cap = std::max<size_t>(need, 2 * b->cap);
+        e = hipStreamSynchronize(b->exec);
+        if (e == hipSuccess) {
+            (void)hipFree(b->d_mem);
+            (void)hipHostFree(b->h_mem);
+            b->d_mem = nullptr;
+            b->h_mem = nullptr;
+            b->cap = 0;
+            e = hipMalloc((void **)&b->d_mem, cap);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_mem, cap, hipHostMallocDefault);
+            if (e == hipSuccess) b->cap = cap;
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "allocating the batch tables");
+
+    char *h = b->h_mem;
+    *at<int64_t>(h, 0) = 0;
+    for (int i = 0; i < n; ++i) {
+        const glbm_solver *m = members[i];
+        at<int32_t>(h, b->o_phase)[i] = m->cur;
+        at<int64_t>(h, b->o_t0)[i] = m->t;
+        for (int c = 0; c < 2; ++c) {
+            KArgs a = m->base;
+            a.src = m->buf[c];
+            a.dst = m->buf[1 - c];
+            a.remap = 0;
+            at<KArgs>(h, b->o_args)[2 * i + c] = a;
+        }
+    }
+    for (size_t k = 0; k < sets.size(); ++k)
+        memcpy(h + sets[k].tiles, lists[k].data(), sizeof(BatchTile) * lists[k].size());
+    e = hipMemcpyAsync(b->d_mem, h, need, hipMemcpyHostToDevice, b->exec);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_staged, b->exec);
+    if (e != hipSuccess) return hip_fail(e, "uploading the batch tables");
+    b->sets = std::move(sets);
+
+    if (b->opt.graph_steps > 0 && !b->sets.empty()) {
+        e = hipStreamBeginCapture(b->exec, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t ec = batch_chunk(b, b->opt.graph_steps);
+            e = hipStreamEndCapture(b->exec, &b->graph);
+            if (ec != hipSuccess) e = ec;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            b->sets.clear();
+            release_graph(b);
+            return hip_fail(e, "capturing the batch graph");
+        }
+    }
+    b->planned = true;
+    return GLBM_OK;
+}
+
+static void set_members(glbm_batch *b, glbm_t *const *members, int32_t n)
+{
+    for (auto *m : b->members) m->in_batch = false;
+    b->members.assign(members, members + n);
+    for (auto *m : b->members) m->in_batch = true;
 }
 
 extern "C" {
@@ -485,21 +670,12 @@ int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_option
     if (o.order < GLBM_ORDER_MEMBER || o.order > GLBM_ORDER_LARGEST_FIRST)
         return fail(GLBM_ERR_INVALID, "unknown tile order");
     if (o.graph_steps < 0) return fail(GLBM_ERR_INVALID, "graph_steps must be >= 0");
-    if (!members || n < 1) return fail(GLBM_ERR_INVALID, "a batch needs at least one member");
-    for (int i = 0; i < n; ++i) {
-        glbm_solver *m = members[i];
-        if (!m) return fail(GLBM_ERR_INVALID, "member %d is NULL", i);
-        if (!m->ready) return fail(GLBM_ERR_STATE, "member %d is not initialised", i);
-        if (m->in_batch) return fail(GLBM_ERR_STATE, "member %d already belongs to a batch", i);
-        for (int j = 0; j < i; ++j)
-            if (members[j] == m) return fail(GLBM_ERR_INVALID, "member %d appears twice", i);
-    }
+    int rc = check_members(members, n, nullptr);
+    if (rc != GLBM_OK) return rc;
 
     glbm_batch *b = new (std::nothrow) glbm_batch();
     if (!b) return fail(GLBM_ERR_INVALID, "out of host memory");
-    b->members.assign(members, members + n);
-    b->block = o.tile_nodes;
-    b->graph_k = o.graph_steps;
+    b->opt = o;
     b->user = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (b->user) {
@@ -510,97 +686,33 @@ int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_option
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
     }
-
-    // per-member arguments for both parities, phase and time origin
-    std::vector<KArgs> args(2 * (size_t)n);
-    std::vector<int32_t> phase(n);
-    std::vector<int64_t> t0(n);
-    for (int i = 0; i < n; ++i) {
-        glbm_solver *m = members[i];
-        for (int c = 0; c < 2; ++c) {
-            KArgs a = m->base;
-            a.src = m->buf[c];
-            a.dst = m->buf[1 - c];
-            a.remap = 0;
-            args[2 * i + c] = a;
-        }
-        phase[i] = m->cur;
-        t0[i] = m->t;
-    }
-    const int64_t zero = 0;
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_args, sizeof(KArgs) * args.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_phase, sizeof(int32_t) * n);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_t0, sizeof(int64_t) * n);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_bstep, sizeof(int64_t));
-    if (e == hipSuccess) e = hipMemcpy(b->d_args, args.data(), sizeof(KArgs) * args.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_phase, phase.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_t0, t0.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_bstep, &zero, sizeof(int64_t), hipMemcpyHostToDevice);
-
-    // tile tables per (variant, row set)
-    struct Part {
-        int member, count;
-        double work;
-    };
-    std::vector<const Variant *> vars;
-    for (auto *m : b->members)
-        if (std::find(vars.begin(), vars.end(), m->var) == vars.end()) vars.push_back(m->var);
-    for (const Variant *v : vars) {
-        const int rowsets[2][2] = {{ROWS_INTERIOR, ROWS_WALLS}, {ROWS_ALL, -1}};
-        for (int rsi = 0; rsi < 2 && e == hipSuccess; ++rsi) {
-            const int rows = rowsets[v->split_rows ? 0 : 1][rsi];
-            if (rows < 0) break;
-            std::vector<Part> parts;
-            for (int i = 0; i < n; ++i) {
-                glbm_solver *m = members[i];
-                if (m->var != v) continue;
-                const int64_t nx = m->geo.nx, ny = m->geo.ny, ly = m->geo.ly;
-                const int64_t cnt = rows == ROWS_ALL ? nx * ny : rows == ROWS_INTERIOR ? (ny - 2 * ly) * nx : 2 * ly * nx;
-                if (cnt > 0) parts.push_back({i, (int)cnt, (double)cnt * m->geo.q});
-            }
-            if (o.order == GLBM_ORDER_LARGEST_FIRST)
-                std::stable_sort(parts.begin(), parts.end(), [](const Part &x, const Part &y) { return x.work > y.work; });
-            std::vector<BatchTile> tiles;
-            if (o.order == GLBM_ORDER_INTERLEAVE) {
-                for (int first = 0;; first += o.tile_nodes) {
-                    bool any = false;
-                    for (const Part &pt : parts)
-                        if (first < pt.count) {
-                            tiles.push_back({pt.member, first, std::min(o.tile_nodes, pt.count - first), 0});
-                            any = true;
-                        }
-                    if (!any) break;
-                }
-            } else {
-                for (const Part &pt : parts)
-                    for (int first = 0; first < pt.count; first += o.tile_nodes)
-                        tiles.push_back({pt.member, first, std::min(o.tile_nodes, pt.count - first), 0});
-            }
-            if (tiles.empty()) continue;
-            glbm_batch::RowSet r{v, rows, nullptr, (int)tiles.size()};
-            e = hipMalloc((void **)&r.d_tiles, sizeof(BatchTile) * tiles.size());
-            if (e == hipSuccess)
-                e = hipMemcpy(r.d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice);
-            b->sets.push_back(r);
-        }
-    }
-
-    // capture one chunk of graph_k steps
-    if (e == hipSuccess && b->graph_k > 0) {
-        e = hipStreamBeginCapture(b->exec, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t ec = batch_chunk(b, b->graph_k);
-            e = hipStreamEndCapture(b->exec, &b->graph);
-            if (ec != hipSuccess) e = ec;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
-    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_staged, hipEventDisableTiming);
     if (e != hipSuccess) {
         batch_free(b);
-        return hip_fail(e, "creating the batch");
+        return hip_fail(e, "creating the batch stream");
     }
-    for (auto *m : b->members) m->in_batch = true;
+    rc = plan(b, members, n);
+    if (rc != GLBM_OK) {
+        batch_free(b);
+        return rc;
+    }
+    set_members(b, members, n);
     *out = b;
+    return GLBM_OK;
+}
+
+int glbm_batch_update(glbm_batch_t *b, glbm_t *const *members, int32_t n)
+{
+    if (!b) return fail(GLBM_ERR_INVALID, "batch is NULL");
+    int rc = check_members(members, n, b);
+    if (rc != GLBM_OK) return rc;
+    rc = plan(b, members, n);
+    if (rc != GLBM_OK) {
+        // keep the old members owned (their state is intact) but unplanned:
+        // stepping fails until a successful update
+        return rc;
+    }
+    set_members(b, members, n);
     return GLBM_OK;
 }
 
@@ -608,7 +720,8 @@ int glbm_batch_step(glbm_batch_t *b, int64_t nsteps)
 {
     if (!b) return fail(GLBM_ERR_INVALID, "batch is NULL");
     if (nsteps < 0) return fail(GLBM_ERR_INVALID, "nsteps must be >= 0");
-    if (nsteps == 0) return GLBM_OK;
+    if (!b->planned) return fail(GLBM_ERR_STATE, "the batch has no valid plan (a previous update failed)");
+    if (nsteps == 0 || b->members.empty()) return GLBM_OK;
     hipError_t e = hipSuccess;
     if (b->own_stream) {
         // order after the caller's earlier work on the default stream
@@ -616,9 +729,9 @@ int glbm_batch_step(glbm_batch_t *b, int64_t nsteps)
         if (e == hipSuccess) e = hipStreamWaitEvent(b->exec, b->ev_in, 0);
     }
     int64_t left = nsteps;
-    while (e == hipSuccess && b->graph_exec && left >= b->graph_k) {
+    while (e == hipSuccess && b->graph_exec && left >= b->opt.graph_steps) {
         e = hipGraphLaunch(b->graph_exec, b->exec);
-        left -= b->graph_k;
+        left -= b->opt.graph_steps;
     }
     while (e == hipSuccess && left > 0) {
         const int k = (int)std::min<int64_t>(left, 1 << 20);

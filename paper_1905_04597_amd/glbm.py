@@ -24,6 +24,7 @@ SYMBOLS = (
     "glbm_population_bytes", "glbm_create", "glbm_init_fields", "glbm_init_populations",
     "glbm_step", "glbm_moments", "glbm_get_populations", "glbm_stats", "glbm_info",
     "glbm_destroy", "glbm_last_error", "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy",
+    "glbm_batch_update",
 )
 ORDER = {"member": 0, "interleave": 1, "largest_first": 2}
 
@@ -102,10 +103,11 @@ def load(path: str = LIB_PATH):
     lib.glbm_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(BatchOptions), vp,
                                       ctypes.POINTER(vp)]
     lib.glbm_batch_step.argtypes = [vp, ctypes.c_int64]
+    lib.glbm_batch_update.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int32]
     lib.glbm_batch_destroy.argtypes = [vp]
     for name in ("glbm_init_fields", "glbm_init_populations", "glbm_step", "glbm_moments",
                  "glbm_get_populations", "glbm_stats", "glbm_info", "glbm_destroy",
-                 "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy"):
+                 "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy", "glbm_batch_update"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -296,6 +298,14 @@ class Batch:
     def step(self, n: int = 1):
         with self._torch.cuda.device(self.device):
             _check(self.lib.glbm_batch_step(self._h, int(n)), "glbm_batch_step")
+
+    def update(self, solvers):
+        """Replace the member set (solvers join and leave between steps)."""
+        solvers = list(solvers)
+        arr = (ctypes.c_void_p * max(1, len(solvers)))(*[s._h.value for s in solvers])
+        with self._torch.cuda.device(self.device):
+            _check(self.lib.glbm_batch_update(self._h, arr, len(solvers)), "glbm_batch_update")
+        self.solvers = solvers
 
     def close(self):
         h = getattr(self, "_h", None)

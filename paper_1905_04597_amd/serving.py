@@ -1,0 +1,288 @@
+"""Continuous-batching server for lattice solves on one GPU.
+
+Requests (a lattice configuration and a step budget) arrive over time.  The
+server keeps every admitted request's populations resident in device memory
+and advances all of them together, a chunk of steps at a time, through
+batches (glbm_batch_*: one launch per kernel variant and step over a table of
+tiles).  Between chunks, finished requests leave (their moments are computed
+on the device and the populations released) and waiting requests join, as
+slots and the device-memory budget allow: continuous batching, not a queue.
+
+Requests are split by size over two lanes, each a batch on its own stream,
+so that the small solves (most requests, little traffic) are not held to the
+pace of the few large ones; the two lanes' kernels share the GPU.  A lane
+re-plans its batch in place (glbm_batch_update) when its members change.
+
+Admission: the population buffers of all active requests (2 x
+glbm_population_bytes each) stay within the budget (default 200 GB); requests
+are admitted first come, first served per lane (a request that does not fit
+waits, and so do the ones behind it in its lane).
+
+Every request's result is bitwise the result of the same solve run alone,
+because a batched lattice runs exactly the single-lattice kernel code.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Optional
+
+import numpy as np
+
+from . import glbm
+from . import workloads as wl
+
+ELEM_BYTES = {"f32": 4, "f32_shifted": 4, "bf16_shifted": 2, "bf16_shifted_sr": 2}
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds after the start of the run
+    workload: wl.Workload
+    steps: int
+    # filled in by the server
+    lane: int = -1
+    nbytes: int = 0           # device bytes of the two population buffers
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    result: Optional[dict] = None   # device moments {rho, ux, uy, T, pxy} when kept
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.finished is None else self.finished - self.arrival
+
+
+def step_bytes(w: wl.Workload) -> int:
+    """Algorithmic HBM bytes of one step (read + write every population)."""
+    return 2 * w.nodes * w.nvel * ELEM_BYTES[w.storage]
+
+
+def make_solver(w: wl.Workload, stream):
+    """Create and initialise the solver of a request on `stream` (its buffers
+    are allocated from that stream, so their reuse is ordered on it)."""
+    import torch
+
+    with torch.cuda.stream(stream):
+        s = glbm.solver_for(w, stream=stream)
+        if w.init == "sod":
+            rho = wl.sod_density(w.nx, w.end_rho[0], w.end_rho[1])
+            s.init_fields(rho, np.zeros_like(rho))
+        else:
+            s.init_fields()
+    return s
+
+
+def solve_alone(w: wl.Workload, steps: int, stream=None) -> dict:
+    """The same solve without the server: one lattice, one launch per step."""
+    import torch
+
+    stream = stream or torch.cuda.current_stream()
+    s = make_solver(w, stream)
+    s.step(steps)
+    with torch.cuda.stream(stream):
+        m = s.moments()
+    stream.synchronize()
+    s.close()
+    return m
+
+
+class _Active:
+    __slots__ = ("req", "solver", "left")
+
+    def __init__(self, req, solver, left):
+        self.req, self.solver, self.left = req, solver, left
+
+
+class _Lane:
+    def __init__(self, index, chunk, slots, batch_opts):
+        import torch
+
+        self.index = index
+        self.chunk = chunk
+        self.slots = slots
+        self.batch_opts = batch_opts
+        self.stream = torch.cuda.Stream()
+        self.event = torch.cuda.Event()
+        self.busy = False
+        self.batch = None
+        self.members: list = []
+        self.leaving: list = []
+        self.changed = False
+        self.waiting = collections.deque()
+        self.chunks = 0
+
+
+class Server:
+    """Continuous batching over two lanes (small and large requests).
+
+    hbm_budget: bytes of population buffers the active requests may hold.
+    light_bytes: a request whose step moves fewer bytes goes to the light lane.
+    chunks: steps per chunk in the (light, heavy) lane.
+    slots: most active requests per lane.
+    keep_results: True, or a set of request ids, whose device moments
+    {rho, ux, uy, T, pxy} are kept in Request.result."""
+
+    def __init__(self, hbm_budget: float = 200e9, light_bytes: int = 64 << 20, chunks=(50, 20),
+                 slots=(4096, 256), tile_nodes: int = 128, order: str = "interleave",
+                 keep_results: bool = False, clock=time.perf_counter):
+        self.hbm_budget = float(hbm_budget)
+        self.light_bytes = int(light_bytes)
+        self.keep_results = keep_results
+        self.clock = clock
+        opts = dict(tile_nodes=tile_nodes, order=order, graph_steps=0)
+        self.lanes = [_Lane(0, chunks[0], slots[0], opts), _Lane(1, chunks[1], slots[1], opts)]
+        self.in_use = 0
+        self.peak_in_use = 0
+
+    def _keep(self, req) -> bool:
+        k = self.keep_results
+        return bool(k) if isinstance(k, bool) else req.rid in k
+
+    # ---------------------------------------------------------------- lanes
+    def _retire(self, lane: _Lane, now: float):
+        """Finished members: record the time and compute their moments (a
+        member of a batch may be observed); they leave at the next plan."""
+        import torch
+
+        done = [a for a in lane.members if a.left <= 0]
+        if not done:
+            return
+        lane.members = [a for a in lane.members if a.left > 0]
+        lane.changed = True
+        for a in done:
+            a.req.finished = now
+            if self._keep(a.req):
+                with torch.cuda.stream(lane.stream):
+                    a.req.result = a.solver.moments()
+            lane.leaving.append(a)
+
+    def _admit(self, lane: _Lane, now: float):
+        while lane.waiting and len(lane.members) < lane.slots:
+            r = lane.waiting[0]
+            if self.in_use + r.nbytes > self.hbm_budget:
+                break
+            lane.waiting.popleft()
+            s = make_solver(r.workload, lane.stream)
+            r.admitted = now
+            self.in_use += r.nbytes
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            lane.members.append(_Active(r, s, r.steps))
+            lane.changed = True
+
+    def _launch(self, lane: _Lane):
+        sol = [a.solver for a in lane.members]
+        if lane.batch is None:
+            if sol:
+                lane.batch = glbm.Batch(sol, stream=lane.stream, **lane.batch_opts)
+        elif lane.changed:
+            lane.batch.update(sol)
+        lane.changed = False
+        # the finished solvers are out of the batch now: release them (their
+        # buffers return to the lane stream's pool after the work queued on it)
+        for a in lane.leaving:
+            a.solver.close()
+            a.solver = None
+            self.in_use -= a.req.nbytes
+        lane.leaving = []
+        if not lane.members:
+            lane.busy = False
+            return
+        k = min(lane.chunk, min(a.left for a in lane.members))
+        lane.batch.step(k)
+        for a in lane.members:
+            a.left -= k
+        lane.event.record(lane.stream)
+        lane.busy = True
+        lane.chunks += 1
+
+    # ------------------------------------------------------------------ run
+    def run(self, arrivals, max_seconds: float = 120.0):
+        """Serve [(arrival seconds, Workload)] in real time; returns the
+        Request records (every request finished unless max_seconds ran out)."""
+        reqs = [Request(i, t, w, w.steps) for i, (t, w) in enumerate(arrivals)]
+        for r in reqs:
+            r.nbytes = 2 * glbm.population_bytes(glbm.config_from_workload(r.workload))
+            if r.nbytes > self.hbm_budget:
+                raise glbm.GlbmError("request %d needs %d bytes, above the budget" % (r.rid, r.nbytes))
+            r.lane = 0 if step_bytes(r.workload) < self.light_bytes else 1
+        pending = collections.deque(sorted(reqs, key=lambda r: r.arrival))
+        t0 = self.clock()
+        while True:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                self.lanes[r.lane].waiting.append(r)
+            for lane in self.lanes:
+                if lane.busy and not lane.event.query():
+                    continue
+                now = self.clock() - t0
+                self._retire(lane, now)
+                self._admit(lane, now)
+                self._launch(lane)
+            idle = not any(l.busy for l in self.lanes)
+            if idle and not pending and not any(l.waiting for l in self.lanes):
+                break
+            if now > max_seconds:
+                break
+            if idle and pending:
+                # nothing on the GPU: wait for the next arrival
+                time.sleep(max(0.0, min(1e-3, pending[0].arrival - (self.clock() - t0))))
+        self.close()
+        return reqs
+
+    def close(self):
+        for lane in self.lanes:
+            lane.stream.synchronize()
+            if lane.batch is not None:
+                lane.batch.update([])
+                lane.batch.close()
+                lane.batch = None
+            for a in lane.members + lane.leaving:
+                a.solver.close()
+                self.in_use -= a.req.nbytes
+            lane.members = []
+            lane.leaving = []
+
+
+def serve_per_solve(arrivals, max_seconds: float = 120.0, clock=time.perf_counter):
+    """The plain per-solve loop on the same arrivals: each request alone, in
+    arrival order, one launch per step, its moments computed before the next
+    one starts."""
+    import torch
+
+    reqs = [Request(i, t, w, w.steps) for i, (t, w) in enumerate(arrivals)]
+    stream = torch.cuda.current_stream()
+    t0 = clock()
+    for r in sorted(reqs, key=lambda r: r.arrival):
+        now = clock() - t0
+        if now > max_seconds:
+            break
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        r.admitted = clock() - t0
+        s = make_solver(r.workload, stream)
+        s.step(r.steps)
+        s.moments()
+        stream.synchronize()
+        s.close()
+        r.finished = clock() - t0
+    return reqs
+
+
+def summarize(reqs, window=(2.0, 12.0)) -> dict:
+    """Throughput and latency of the requests that arrived inside `window`."""
+    lo, hi = window
+    meas = [r for r in reqs if lo <= r.arrival < hi]
+    done = [r for r in meas if r.finished is not None]
+    lat = np.array(sorted(r.latency for r in done)) if done else np.array([np.nan])
+    span = (max(r.finished for r in done) - lo) if done else float("nan")
+    return {
+        "requests": len(meas), "completed": len(done),
+        "solves_per_s": round(len(done) / span, 2) if done else 0.0,
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+        "latency_max_s": round(float(lat.max()), 4),
+        "node_steps": int(sum(r.workload.nodes * r.steps for r in done)),
+    }

@@ -162,5 +162,52 @@ def sweep_workloads(count: int = 512, seed: int = 190504597, steps: int = 2000,
     return out
 
 
+def log_uniform(rng, lo: float, hi: float) -> float:
+    return float(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+
+
+def served_requests(rate: float = 200.0, duration: float = 12.0, arrival_seed: int = 1905,
+                    param_seed: int = 4597, sod_steps: int = 1000, channel_steps: int = 200,
+                    storages=("f32_shifted", "bf16_shifted_sr")):
+    """The served mix: Poisson arrivals at `rate` per second over `duration`
+    seconds (arrival seed), each a Sod, Couette or Poiseuille solve with equal
+    odds (parameter seed): level N ~ U{1..7} (k = N - 1 in 0..6), log10 Kn ~
+    U[-3, 1], storage FP32 or BF16 deviations with equal odds; Sod over
+    log-uniform 500..20000 nodes for `sod_steps` steps; channels with Ny and
+    Nx log-uniform in [32, 2048] and [4, 2048], wall speed (Couette) or
+    centre-line speed (Poiseuille) ~ U[0.01, 0.1] c_s, `channel_steps` steps.
+    Every request draws all fields, so the parameter stream does not depend
+    on the drawn kinds.  Returns [(arrival seconds, Workload)]."""
+    ra = np.random.default_rng(arrival_seed)
+    rp = np.random.default_rng(param_seed)
+    out = []
+    t = 0.0
+    while True:
+        t += float(ra.exponential(1.0 / rate))
+        if t >= duration:
+            break
+        kind = ("sod", "couette", "poiseuille")[int(rp.integers(0, 3))]
+        level = int(rp.integers(1, 8))
+        kn = float(10 ** rp.uniform(-3, 1))
+        storage = storages[int(rp.integers(0, len(storages)))]
+        sod_nodes = int(round(log_uniform(rp, 500, 20000)))
+        ny = int(round(log_uniform(rp, 32, 2048)))
+        nx = int(round(log_uniform(rp, 4, 2048)))
+        speed = float(rp.uniform(0.01, 0.1)) * sound_speed(level)
+        if kind == "sod":
+            w = sod(sod_nodes, level=level, kn=kn, steps=sod_steps, storage=storage)
+        elif kind == "couette":
+            w = couette(kn, ny=ny, nx=nx, level=level, steps=channel_steps, storage=storage)
+            w.wall_u = (-speed, speed)
+        else:
+            theta = level / 3.0
+            nu = theta * kn * ny / math.sqrt(2.0 * theta)
+            w = poiseuille(nx=nx, ny=ny, level=level, kn=kn, g=8.0 * nu * speed / (ny * ny),
+                           steps=channel_steps, storage=storage)
+        w.name = "%s_%d" % (kind, len(out))
+        out.append((t, w))
+    return out
+
+
 def maybe_f64(a: Optional[np.ndarray]):
     return None if a is None else np.asarray(a, dtype=np.float64)

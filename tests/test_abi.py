@@ -99,3 +99,4 @@ def test_batch_entry_points_reject_bad_arguments_without_touching_the_gpu():
     assert lib.glbm_batch_create(None, 1, None, None, None) == -1
     assert lib.glbm_batch_step(None, 1) == -1
     assert lib.glbm_batch_destroy(None) == 0
+    assert lib.glbm_batch_update(None, None, 0) == -1

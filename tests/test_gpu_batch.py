@@ -92,6 +92,35 @@ def test_batch_bitwise_equals_alone(opts):
     _assert_bitwise(alone, batched, "after leaving the batch")
 
 
+def test_batch_update_joins_and_leaves_bitwise():
+    """Continuous batching: members join and leave between chunks of steps
+    (glbm_batch_update re-plans the tables in place); every lattice still
+    matches its twin stepped alone, bitwise."""
+    import torch
+
+    alone, batched = _pair(MEMBERS)
+    stream = torch.cuda.Stream()
+    # the batch runs on its own stream: hand the members over through a sync
+    torch.cuda.synchronize()
+    schedule = [([0, 1, 2], 7), ([1, 2, 3, 4, 5], 5), ([5, 6, 7, 8], 9), ([0, 8], 4), (list(range(9)), 6)]
+    steps = [0] * len(MEMBERS)
+    b = None
+    for members, k in schedule:
+        sol = [batched[i] for i in members]
+        if b is None:
+            b = glbm.Batch(sol, tile_nodes=64, order="interleave", graph_steps=3, stream=stream)
+        else:
+            b.update(sol)
+        b.step(k)
+        for i in members:
+            steps[i] += k
+    stream.synchronize()
+    b.close()
+    for s, n in zip(alone, steps):
+        s.step(n)
+    _assert_bitwise(alone, batched, "after joins and leaves")
+
+
 def test_member_of_a_batch_cannot_step_alone():
     s = _solver(MEMBERS[0])
     _init(s, MEMBERS[0], 1)
