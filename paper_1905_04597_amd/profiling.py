@@ -4,6 +4,7 @@ counters), written as short text under ``profiles/``.
     python -m paper_1905_04597_amd.profiling --workload NAME --storage S \\
         --trace DIR/kt_results.db --fetch DIR/pmc_results.db --write DIR/pmc_results.db \\
         --command "the rocprofv3 command lines" [--copy-bytes 2147483648]
+    python -m paper_1905_04597_amd.profiling batched --trace DIR/kt_results.db --command "..."
 
 The memory counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled
 by what they read for a plain device copy of known size in the same run
@@ -51,7 +52,62 @@ def counter(db_path: str, name: str):
     return {key: statistics.median(vs) for key, vs in by.items()}
 
 
+def batched_summary(trace: str, command: str, count: int = 512, storage: str = "f32_shifted"):
+    """Per-level averages of the batched step kernel over the channel sweep:
+    each launch steps every instance of one level once, so its algorithmic
+    bytes are the sum of 2 Q s nodes over those instances."""
+    import re
+
+    from . import workloads as wl
+
+    eb = 4 if storage.startswith("f32") else 2
+    per_level = {}
+    for w in wl.sweep_workloads(count, storage=storage):
+        per_level[w.level_x] = per_level.get(w.level_x, 0) + 2 * w.nvel * eb * w.nodes
+    stats = kernel_stats(trace)
+    rows = []
+    for st in stats:
+        m = re.search(r"batch_step_kernel<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+)>", st["name"])
+        if not m:
+            continue
+        lx = int(m.group(1))
+        b = per_level.get(lx)
+        if b is None:
+            continue
+        rows.append((lx, st["calls"], st["avg_us"], b, b / (st["avg_us"] * 1e-6) / 1e9))
+    rows.sort()
+    path = os.path.join(PROFILES, "batch_step_kernel_channel_sweep_%d.md" % count)
+    with open(path, "w") as fh:
+        fh.write("# Batched step kernel, channel sweep of %d instances (Nx = 4, storage %s)\n\n" % (count, storage))
+        fh.write("Command (run on one MI355X):\n\n```\n%s\n```\n\n" % command.strip())
+        fh.write("## rocprofv3 --kernel-trace --stats (top kernels)\n\n| kernel | calls | avg us | total us | % |\n"
+                 "|---|---|---|---|---|\n")
+        for st in stats[:12]:
+            fh.write("| `%s` | %d | %.1f | %.1f | %.2f |\n" % (st["name"][:90], st["calls"], st["avg_us"], st["total_us"],
+                                                           st["pct"]))
+        fh.write("\n## Per level: one launch steps every instance of the level once\n\n"
+                 "| level N | launches | avg us | algorithmic bytes / launch | GB/s |\n|---|---|---|---|---|\n")
+        for lx, calls, avg, b, gbs in rows:
+            fh.write("| %d | %d | %.1f | %.4g | %.0f |\n" % (lx, calls, avg, b, gbs))
+        tot_us = sum(r[2] for r in rows)
+        tot_b = sum(r[3] for r in rows)
+        fh.write("\nOne step of the whole sweep: %.1f us of batched kernels for %.4g algorithmic bytes, "
+                 "%.0f GB/s.\n" % (tot_us, tot_b, tot_b / (tot_us * 1e-6) / 1e9))
+        fh.write("- kernel source hash: %s\n" % kernel_source_hash())
+    print(path)
+
+
 def main(argv=None):
+    import sys
+
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "batched":
+        bp = argparse.ArgumentParser()
+        bp.add_argument("--trace", required=True)
+        bp.add_argument("--command", required=True)
+        bp.add_argument("--count", type=int, default=512)
+        b = bp.parse_args(argv[1:])
+        return batched_summary(b.trace, b.command, b.count)
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", required=True)
     ap.add_argument("--storage", required=True)
