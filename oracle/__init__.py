@@ -6,10 +6,14 @@ The arithmetic lives in ``glbm_oracle.c`` (plain C, FP64); this module only
 builds it with gcc and marshals numpy arrays through ctypes.
 """
 from .oracle import (  # noqa: F401
+    AXIS_EVEN,
+    AXIS_ODD,
     BC_EQ_ENDS,
     BC_PERIODIC,
     BC_WALL,
     OracleSolver,
+    axis_equilibrium,
+    axis_velocities,
     build_oracle,
     equilibrium_1d,
     rest_weights,

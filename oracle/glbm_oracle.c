@@ -16,10 +16,18 @@
  * same model rescaled; orc_equilibrium_1d takes c and theta0 explicitly so
  * that it can also be evaluated in those units.
  *
+ * Two kinds of axis (section 2):
+ *   ORC_AXIS_ODD  - G-D1Q(2N+1): velocities n = -N..N (index a = n + N),
+ *                   theta = N/3;
+ *   ORC_AXIS_EVEN - G-D1Q(2N+2), zero velocity removed
+ *                   (Eqs. maineq01_noball-maineq04_noball): velocities
+ *                   (n + 1/2) c of the lattice step c, here on a grid of half
+ *                   that step (c = 2 nodes), i.e. the odd integers
+ *                   v = 2a - (2N+1), a = 0..2N+1; by Eq. temp_2N2 the
+ *                   temperature is theta = (4N+3) c^2 / 12 = (4N+3)/3.
  * Velocity ordering and state layout (shared by every array here):
- *   axis x has level Lx (velocities a - Lx, a = 0..2Lx), axis y level Ly
- *   (Ly = 0 in one dimension: a single velocity 0);
- *   q = b * (2Lx+1) + a;  arrays are [q][y][x], x fastest.
+ *   axis x has Qx velocities cx[a], axis y Qy velocities cy[b] (one velocity
+ *   0 in one dimension); q = b * Qx + a;  arrays are [q][y][x], x fastest.
  *
  * Parity status of each function is stated in its comment; every one of
  * them is pinned by a CPU test (closed forms, worked example of Appendix A,
@@ -33,6 +41,8 @@
 #define ORC_BC_PERIODIC 0
 #define ORC_BC_WALL 1     /* diffuse-reflection wall (only on y) */
 #define ORC_BC_EQ_ENDS 2  /* fixed equilibrium ends (only on x) */
+#define ORC_AXIS_ODD 0
+#define ORC_AXIS_EVEN 1
 
 /* ------------------------------------------------------------------ */
 /* Equilibrium of one axis: section 2, Eqs. maineq02-maineq04 and the   */
@@ -81,6 +91,27 @@ void orc_step_probabilities(int N, double c, double theta0, double u, double *ou
     out3[1] = 1.0 - out3[0] - out3[2];
 }
 
+/* Equilibrium at rho = 1 of one axis in lattice units (unit grid spacing).
+ * ODD: Eq. maineq03 with c = 1, theta0 = N/3.  EVEN: the 2N+1 equilibrium on
+ * the lattice of step c = 2 (theta0 = N c^2 / 3), each velocity (n + 1/2) c
+ * taking the average of the states at its two neighbours n c and (n + 1) c
+ * (Eqs. maineq01_noball-maineq04_noball; the outermost ones have a single
+ * neighbour).  out has 2N+1 (ODD) or 2N+2 (EVEN) entries. */
+void orc_axis_equilibrium(int kind, int N, double u, double *out)
+{
+    if (kind == ORC_AXIS_ODD) {
+        orc_equilibrium_1d(N, 1.0, N / 3.0, u, out);
+        return;
+    }
+    double F[64];
+    orc_equilibrium_1d(N, 2.0, 4.0 * N / 3.0, u, F);
+    for (int a = 0; a <= 2 * N + 1; ++a) {
+        const double lo = a >= 1 ? F[a - 1] : 0.0;    /* neighbour n c, n = a - N - 1 */
+        const double hi = a <= 2 * N ? F[a] : 0.0;     /* neighbour (n + 1) c */
+        out[a] = 0.5 * (lo + hi);
+    }
+}
+
 /* Relaxation time from the Knudsen number of Eq. kn (section 5.2):
  * Kn = sqrt(2/theta) nu / H with nu = theta tau, hence
  * tau = Kn H / sqrt(2 theta). */
@@ -95,13 +126,16 @@ double orc_tau_from_kn(double kn, double H, double theta)
 
 typedef struct orc_solver {
     int dims, Lx, Ly;
+    int kx, ky;       /* axis kinds (ORC_AXIS_*) */
+    int cx[64], cy[64]; /* velocities of the two axes */
+    double u2x, u2y;  /* positivity bounds on u^2 of the two axes (section 3) */
     int64_t nx, ny;
     double tau, omega, g;
     int bc_x, bc_y;
     double wall_u[2]; /* x velocity of the bottom (y = -1/2) and top (y = ny - 1/2) wall */
     double end_rho[2];/* densities of the fixed equilibrium ends (x < 0, x >= nx) */
     int Qx, Qy, Q;
-    double thx, thy;  /* axis temperatures N/3 in lattice units */
+    double thx, thy;  /* axis temperatures in lattice units */
     double *Wx, *Wy;  /* rest weights: equilibrium at rho = 1, u = 0 */
     double Jplus_y;   /* half flux sum_{n>0} n W_n of the wall-normal axis */
     double *Ebot, *Etop; /* wall emission per velocity at unit wall density */
@@ -121,29 +155,60 @@ static int64_t imod(int64_t a, int64_t m)
 
 static inline int64_t nodes(const orc_solver *s) { return s->nx * s->ny; }
 
+/* Velocities, temperature and positivity bound of an axis.  Positivity
+ * (section 3): P0 >= 0 of the underlying 2N+1 model, u^2 <= 2 N theta0 with
+ * theta0 = N c^2 / 3 of its lattice step c (1 for ODD, 2 for EVEN). */
+static int axis_setup(int kind, int N, int *vel, double *theta, double *u2max)
+{
+    if (kind == ORC_AXIS_ODD) {
+        for (int a = 0; a <= 2 * N; ++a) vel[a] = a - N;
+        *theta = N / 3.0;
+        *u2max = 2.0 * N * (N / 3.0);
+        return 2 * N + 1;
+    }
+    for (int a = 0; a <= 2 * N + 1; ++a) vel[a] = 2 * a - (2 * N + 1);
+    *theta = (4.0 * N + 3.0) / 3.0;
+    *u2max = 2.0 * N * (4.0 * N / 3.0);
+    return 2 * N + 2;
+}
+
 /* Create a solver.  Returns NULL on an invalid configuration.
+ * kind_x, kind_y: ORC_AXIS_ODD or ORC_AXIS_EVEN (ignored for the absent y
+ * axis of one dimension).
  * tau > 0 is used as given; tau <= 0 derives it from kn (Eq. kn) with the
  * wall distance H = ny (walls half way between nodes) in two dimensions, or
  * the domain length H = nx in one dimension; tau = +inf gives omega = 0. */
-orc_solver *orc_create(int dims, int Lx, int Ly, int64_t nx, int64_t ny, double tau, double kn,
-                       int bc_x, int bc_y, const double *wall_u, const double *end_rho, double g)
+orc_solver *orc_create(int dims, int Lx, int Ly, int kind_x, int kind_y, int64_t nx, int64_t ny, double tau,
+                       double kn, int bc_x, int bc_y, const double *wall_u, const double *end_rho, double g)
 {
     if (dims != 1 && dims != 2) return NULL;
-    if (dims == 1) { Ly = 0; ny = 1; bc_y = ORC_BC_PERIODIC; }
+    if (dims == 1) { Ly = 0; ny = 1; bc_y = ORC_BC_PERIODIC; kind_y = ORC_AXIS_ODD; }
     if (Lx < 1 || (dims == 2 && Ly < 1) || nx < 1 || ny < 1) return NULL;
-    if (Lx > 31 || Ly > 31 || (2 * Lx + 1) * (2 * Ly + 1) > 4096) return NULL;
+    if (Lx > 30 || Ly > 30) return NULL;
+    if ((kind_x != ORC_AXIS_ODD && kind_x != ORC_AXIS_EVEN) || (kind_y != ORC_AXIS_ODD && kind_y != ORC_AXIS_EVEN))
+        return NULL;
     if (bc_x != ORC_BC_PERIODIC && bc_x != ORC_BC_EQ_ENDS) return NULL;
     if (bc_y != ORC_BC_PERIODIC && bc_y != ORC_BC_WALL) return NULL;
     if (bc_x == ORC_BC_EQ_ENDS && bc_y == ORC_BC_WALL) return NULL;
-    if (bc_y == ORC_BC_WALL && ny < 2 * Ly) return NULL;
 
     orc_solver *s = (orc_solver *)calloc(1, sizeof(orc_solver));
     s->dims = dims; s->Lx = Lx; s->Ly = Ly; s->nx = nx; s->ny = ny;
+    s->kx = kind_x; s->ky = kind_y;
     s->bc_x = bc_x; s->bc_y = bc_y; s->g = g;
     s->wall_u[0] = wall_u ? wall_u[0] : 0.0; s->wall_u[1] = wall_u ? wall_u[1] : 0.0;
     s->end_rho[0] = end_rho ? end_rho[0] : 1.0; s->end_rho[1] = end_rho ? end_rho[1] : 1.0;
-    s->Qx = 2 * Lx + 1; s->Qy = 2 * Ly + 1; s->Q = s->Qx * s->Qy;
-    s->thx = Lx / 3.0; s->thy = Ly / 3.0;
+    s->Qx = axis_setup(kind_x, Lx, s->cx, &s->thx, &s->u2x);
+    if (dims == 2) {
+        s->Qy = axis_setup(kind_y, Ly, s->cy, &s->thy, &s->u2y);
+    } else {
+        s->Qy = 1; s->cy[0] = 0; s->thy = 0.0; s->u2y = 0.0;
+    }
+    s->Q = s->Qx * s->Qy;
+    /* no population may cross both walls in one step */
+    if (s->Q > 4096 || (bc_y == ORC_BC_WALL && ny < 2 * s->cy[s->Qy - 1])) {
+        free(s);
+        return NULL;
+    }
     if (tau > 0.0) {
         s->tau = tau;
     } else {
@@ -156,17 +221,18 @@ orc_solver *orc_create(int dims, int Lx, int Ly, int64_t nx, int64_t ny, double 
 
     s->Wx = (double *)calloc(s->Qx, sizeof(double));
     s->Wy = (double *)calloc(s->Qy, sizeof(double));
-    orc_equilibrium_1d(Lx, 1.0, s->thx, 0.0, s->Wx);
-    orc_equilibrium_1d(Ly, 1.0, s->thy, 0.0, s->Wy);
+    orc_axis_equilibrium(kind_x, Lx, 0.0, s->Wx);
+    if (dims == 2) orc_axis_equilibrium(kind_y, Ly, 0.0, s->Wy); else s->Wy[0] = 1.0;
     s->Jplus_y = 0.0;
-    for (int n = 1; n <= Ly; ++n) s->Jplus_y += n * s->Wy[n + Ly];
+    for (int b = 0; b < s->Qy; ++b)
+        if (s->cy[b] > 0) s->Jplus_y += s->cy[b] * s->Wy[b];
 
     s->Ebot = (double *)calloc(s->Q, sizeof(double));
     s->Etop = (double *)calloc(s->Q, sizeof(double));
     double *Fb = (double *)calloc(s->Qx, sizeof(double));
     double *Ft = (double *)calloc(s->Qx, sizeof(double));
-    orc_equilibrium_1d(Lx, 1.0, s->thx, s->wall_u[0], Fb);
-    orc_equilibrium_1d(Lx, 1.0, s->thx, s->wall_u[1], Ft);
+    orc_axis_equilibrium(kind_x, Lx, s->wall_u[0], Fb);
+    orc_axis_equilibrium(kind_x, Lx, s->wall_u[1], Ft);
     for (int b = 0; b < s->Qy; ++b)
         for (int a = 0; a < s->Qx; ++a) {
             const int q = b * s->Qx + a;
@@ -200,6 +266,13 @@ double orc_omega(const orc_solver *s) { return s->omega; }
 int64_t orc_time(const orc_solver *s) { return s->t; }
 int orc_nvel(const orc_solver *s) { return s->Q; }
 
+int orc_axis_velocities(const orc_solver *s, int *cx, int *cy)
+{
+    memcpy(cx, s->cx, sizeof(int) * s->Qx);
+    memcpy(cy, s->cy, sizeof(int) * s->Qy);
+    return s->Qx;
+}
+
 /* Rest weights of the two axes and the wall-normal half flux. */
 void orc_tables(const orc_solver *s, double *Wx, double *Wy, double *jplus)
 {
@@ -212,8 +285,8 @@ void orc_tables(const orc_solver *s, double *Wx, double *Wy, double *jplus)
 static void equilibrium_node(const orc_solver *s, double rho, double ux, double uy, double *feq)
 {
     double Fx[64], Fy[64];
-    orc_equilibrium_1d(s->Lx, 1.0, s->thx, ux, Fx);
-    orc_equilibrium_1d(s->Ly, 1.0, s->thy, uy, Fy);
+    orc_axis_equilibrium(s->kx, s->Lx, ux, Fx);
+    if (s->dims == 2) orc_axis_equilibrium(s->ky, s->Ly, uy, Fy); else Fy[0] = 1.0;
     for (int b = 0; b < s->Qy; ++b)
         for (int a = 0; a < s->Qx; ++a) feq[b * s->Qx + a] = rho * Fx[a] * Fy[b];
 }
@@ -251,8 +324,8 @@ static void node_rho_u(const orc_solver *s, const double *f, int64_t k, double *
         for (int a = 0; a < s->Qx; ++a) {
             const double v = f[(b * s->Qx + a) * n + k];
             r += v;
-            jx += v * (a - s->Lx);
-            jy += v * (b - s->Ly);
+            jx += v * s->cx[a];
+            jy += v * s->cy[b];
         }
     *rho = r; *ux = jx / r; *uy = jy / r;
 }
@@ -272,7 +345,7 @@ static void collide_all(const orc_solver *s, const double *f, double *fs, double
         for (int b = 0; b < s->Qy; ++b)
             for (int a = 0; a < s->Qx; ++a) {
                 const int q = b * s->Qx + a;
-                const double force = s->Wx[a] * s->Wy[b] * (a - s->Lx) * s->g / s->thx;
+                const double force = s->Wx[a] * s->Wy[b] * s->cx[a] * s->g / s->thx;
                 const double v = f[q * n + k];
                 fs[q * n + k] = v + s->omega * (feq[q] - v) + force;
             }
@@ -285,7 +358,7 @@ static void collide_all(const orc_solver *s, const double *f, double *fs, double
  * is absorbed and attributed to the column it would have reached; the wall
  * re-emits that mass into the same column as the equilibrium at the wall
  * velocity, rho_w(x) E_i, over the populations that point into the fluid,
- * so rho_w(x) = absorbed(x) / J+ with J+ = sum_{n>0} n W_n. */
+ * so rho_w(x) = absorbed(x) / J+ with J+ = sum_{c>0} c W_c. */
 static void wall_densities(const orc_solver *s, const double *fs, double *rw_bot, double *rw_top,
                            double *mom_bot, double *mom_top)
 {
@@ -293,9 +366,9 @@ static void wall_densities(const orc_solver *s, const double *fs, double *rw_bot
     for (int64_t x = 0; x < nx; ++x) {
         double ab = 0, at = 0, pb = 0, pt = 0;
         for (int b = 0; b < s->Qy; ++b) {
-            const int cb = b - s->Ly;
+            const int cb = s->cy[b];
             for (int a = 0; a < s->Qx; ++a) {
-                const int ca = a - s->Lx;
+                const int ca = s->cx[a];
                 const int q = b * s->Qx + a;
                 const int64_t xs = imod(x - ca, nx);
                 if (cb < 0) {
@@ -325,9 +398,9 @@ static void stream_all(const orc_solver *s, const double *fs, double *fn)
 {
     const int64_t n = nodes(s), nx = s->nx, ny = s->ny;
     for (int b = 0; b < s->Qy; ++b) {
-        const int cb = b - s->Ly;
+        const int cb = s->cy[b];
         for (int a = 0; a < s->Qx; ++a) {
-            const int ca = a - s->Lx;
+            const int ca = s->cx[a];
             const int q = b * s->Qx + a;
             for (int64_t y = 0; y < ny; ++y)
                 for (int64_t x = 0; x < nx; ++x) {
@@ -377,7 +450,7 @@ void orc_moments(const orc_solver *s, double *rho, double *ux, double *uy, doubl
         for (int b = 0; b < s->Qy; ++b)
             for (int a = 0; a < s->Qx; ++a) {
                 const double v = s->f[(b * s->Qx + a) * n + k];
-                const double ca = a - s->Lx, cb = b - s->Ly;
+                const double ca = s->cx[a], cb = s->cy[b];
                 r += v; jx += v * ca; jy += v * cb;
                 exx += v * ca * ca; eyy += v * cb * cb; exy += v * ca * cb;
             }
@@ -411,8 +484,8 @@ static void kadd(ksum *k, double v)
  *  out[6] absorbed mass at the top wall
  *  out[7] x momentum given to the bottom wall in the next streaming
  *  out[8] x momentum given to the top wall
- *  out[9] number of nodes outside the positivity domain |u| <= sqrt(2 N theta)
- *         of section 3 on either axis */
+ *  out[9] number of nodes outside the positivity domain of section 3 on
+ *         either axis (see axis_setup) */
 void orc_stats(orc_solver *s, double *out)
 {
     const int64_t n = nodes(s), nx = s->nx;
@@ -425,7 +498,7 @@ void orc_stats(orc_solver *s, double *out)
         for (int b = 0; b < s->Qy; ++b)
             for (int a = 0; a < s->Qx; ++a) {
                 const int q = b * s->Qx + a;
-                const double ca = a - s->Lx, cb = b - s->Ly;
+                const double ca = s->cx[a], cb = s->cy[b];
                 const double v = s->f[q * n + k];
                 r += v; jx += v * ca; jy += v * cb;
                 en += s->fs[q * n + k] * (ca * ca + cb * cb);
@@ -434,7 +507,7 @@ void orc_stats(orc_solver *s, double *out)
         kadd(&u2, ux[k] * ux[k]);
         kadd(&d2, (ux[k] - s->ux_prev[k]) * (ux[k] - s->ux_prev[k]));
         const double vy = jy / r;
-        if (ux[k] * ux[k] > 2.0 * s->Lx * s->thx || (s->Ly > 0 && vy * vy > 2.0 * s->Ly * s->thy)) npos += 1;
+        if (ux[k] * ux[k] > s->u2x || (s->dims == 2 && vy * vy > s->u2y)) npos += 1;
     }
     out[0] = m.s; out[1] = px.s; out[2] = py.s; out[3] = e.s;
     out[4] = s->t > 0 ? sqrt(d2.s) / sqrt(u2.s) : NAN;

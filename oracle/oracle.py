@@ -1,8 +1,10 @@
 """ctypes binding of the FP64 oracle (``glbm_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Arrays use the
-oracle's layout: populations ``[q][y][x]`` with ``q = b*(2Lx+1) + a``,
-velocity ``(a - Lx, b - Ly)``; node fields ``[y][x]``.
+oracle's layout: populations ``[q][y][x]`` with ``q = b*Qx + a`` and velocity
+``(cx[a], cy[b])`` (``velocities()``): ``a - N`` on a G-D1Q(2N+1) axis, the odd
+integers ``2a - (2N+1)`` on a G-D1Q(2N+2) axis (grid of half the lattice
+step); node fields ``[y][x]``.
 """
 from __future__ import annotations
 
@@ -16,6 +18,8 @@ import numpy as np
 BC_PERIODIC = 0
 BC_WALL = 1
 BC_EQ_ENDS = 2
+AXIS_ODD = 0
+AXIS_EVEN = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "glbm_oracle.c")
@@ -51,8 +55,10 @@ def _load():
         lib.orc_step_probabilities.restype = None
         lib.orc_tau_from_kn.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         lib.orc_tau_from_kn.restype = ctypes.c_double
+        lib.orc_axis_equilibrium.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+        lib.orc_axis_equilibrium.restype = None
         lib.orc_create.argtypes = [
-            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double,
         ]
         lib.orc_create.restype = ctypes.c_void_p
@@ -66,6 +72,8 @@ def _load():
         lib.orc_nvel.argtypes = [ctypes.c_void_p]
         lib.orc_nvel.restype = ctypes.c_int
         lib.orc_tables.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        lib.orc_axis_velocities.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        lib.orc_axis_velocities.restype = ctypes.c_int
         lib.orc_init_fields.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         lib.orc_init_populations.argtypes = [ctypes.c_void_p, _dp]
         lib.orc_get_populations.argtypes = [ctypes.c_void_p, _dp]
@@ -113,9 +121,23 @@ def step_probabilities(N: int, u: float, c: float = 1.0, theta0: float | None = 
     return out
 
 
-def rest_weights(N: int) -> np.ndarray:
-    """Equilibrium at rho = 1, u = 0 (the weights W_n used by the force term)."""
-    return equilibrium_1d(N, 0.0)
+def rest_weights(N: int, even: bool = False) -> np.ndarray:
+    """Equilibrium at rho = 1, u = 0 (the weights W used by the force term)."""
+    return axis_equilibrium(N, 0.0, even)
+
+
+def axis_equilibrium(N: int, u: float, even: bool = False) -> np.ndarray:
+    """Equilibrium at rho = 1 of an axis in lattice units (unit grid spacing):
+    G-D1Q(2N+1) at velocities -N..N, or G-D1Q(2N+2) at the odd velocities
+    -(2N+1)..2N+1 (Eqs. maineq01_noball-maineq04_noball)."""
+    lib = _load()
+    out = np.zeros(2 * N + 2 if even else 2 * N + 1)
+    lib.orc_axis_equilibrium(AXIS_EVEN if even else AXIS_ODD, int(N), float(u), _ptr(out))
+    return out
+
+
+def axis_velocities(N: int, even: bool = False) -> np.ndarray:
+    return np.arange(-(2 * N + 1), 2 * N + 2, 2) if even else np.arange(-N, N + 1)
 
 
 def tau_from_kn(kn: float, H: float, theta: float) -> float:
@@ -132,11 +154,13 @@ class OracleSolver:
     )
 
     def __init__(self, dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0,
-                 bc_x=BC_PERIODIC, bc_y=BC_PERIODIC, wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0):
+                 bc_x=BC_PERIODIC, bc_y=BC_PERIODIC, wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0,
+                 even_x=False, even_y=False):
         self._lib = _load()
         wu = np.asarray(wall_u, dtype=np.float64)
         er = np.asarray(end_rho, dtype=np.float64)
-        h = self._lib.orc_create(int(dims), int(level_x), int(level_y), int(nx), int(ny),
+        h = self._lib.orc_create(int(dims), int(level_x), int(level_y), AXIS_EVEN if even_x else AXIS_ODD,
+                                 AXIS_EVEN if even_y else AXIS_ODD, int(nx), int(ny),
                                  float(tau), float(kn), int(bc_x), int(bc_y), _ptr(wu), _ptr(er), float(g))
         if not h:
             raise ValueError("oracle rejected the configuration")
@@ -147,6 +171,12 @@ class OracleSolver:
         self.nx = int(nx)
         self.ny = int(ny) if dims == 2 else 1
         self.Q = self._lib.orc_nvel(h)
+        cx = (ctypes.c_int * 64)()
+        cy = (ctypes.c_int * 64)()
+        self.Qx = self._lib.orc_axis_velocities(h, cx, cy)
+        self.Qy = self.Q // self.Qx
+        self.cx = np.array(cx[:self.Qx])
+        self.cy = np.array(cy[:self.Qy])
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -170,9 +200,12 @@ class OracleSolver:
     def nodes(self):
         return self.nx * self.ny
 
+    def velocities(self):
+        return self.cx.copy(), self.cy.copy()
+
     def tables(self):
-        Wx = np.zeros(2 * self.level_x + 1)
-        Wy = np.zeros(2 * self.level_y + 1)
+        Wx = np.zeros(self.Qx)
+        Wy = np.zeros(self.Qy)
         jp = np.zeros(1)
         self._lib.orc_tables(self._h, _ptr(Wx), _ptr(Wy), _ptr(jp))
         return Wx, Wy, float(jp[0])

@@ -9,6 +9,12 @@ through a diffuse wall are absorbed per destination column and re-emitted as
 the unit-density equilibrium at the wall velocity scaled so that the column
 keeps its mass; populations pushed out of a fixed-equilibrium end are lost
 and the end supplies equilibrium populations at rest.
+
+An axis is a G-D1Q(2N+1) axis (velocities -N..N) or, with ``even``, a
+G-D1Q(2N+2) axis on the grid of half its lattice step: velocities the odd
+integers up to 2N+1, its equilibrium the law of the N-step sum on the
+doubled lattice (steps -2, 0, 2) plus an independent fair step of -1 or +1
+(the neighbour average of section 2, read as a random walk).
 """
 from __future__ import annotations
 
@@ -35,15 +41,34 @@ def dice_law(N: int, u: float) -> dict:
     return dict(law)
 
 
-def run(dims, Lx, Ly, nx, ny, omega, g, bc_x, bc_y, wall_u, end_rho, f0, steps):
+def even_law(N: int, u: float) -> dict:
+    """Sum of N steps in {-2, 0, 2} (mean u/N, the doubled lattice of
+    temperature 4N/3) plus a fair step in {-1, +1}."""
+    half = dice_law(N, u / 2.0)
+    law = defaultdict(float)
+    for k, p in half.items():
+        law[2 * k + 1] += 0.5 * p
+        law[2 * k - 1] += 0.5 * p
+    return dict(law)
+
+
+def axis_law(N: int, even: bool, u: float) -> dict:
+    return even_law(N, u) if even else dice_law(N, u)
+
+
+def axis_velocities(N: int, even: bool):
+    return list(range(-(2 * N + 1), 2 * N + 2, 2)) if even else list(range(-N, N + 1))
+
+
+def run(dims, Lx, Ly, nx, ny, omega, g, bc_x, bc_y, wall_u, end_rho, f0, steps, even_x=False, even_y=False):
     """Advance ``f0`` (a dict {(x, y, cx, cy): value}) by ``steps`` steps."""
     if dims == 1:
-        Ly, ny, bc_y = 0, 1, PERIODIC
-    vel = [(cx, cy) for cy in range(-Ly, Ly + 1) for cx in range(-Lx, Lx + 1)]
-    Wx, Wy = dice_law(Lx, 0.0), dice_law(Ly, 0.0)
-    thx = Lx / 3.0
-    jplus = sum(cy * Wy[cy] for cy in range(1, Ly + 1))
-    Fbot, Ftop = dice_law(Lx, wall_u[0]), dice_law(Lx, wall_u[1])
+        Ly, ny, bc_y, even_y = 0, 1, PERIODIC, False
+    vel = [(cx, cy) for cy in axis_velocities(Ly, even_y) for cx in axis_velocities(Lx, even_x)]
+    Wx, Wy = axis_law(Lx, even_x, 0.0), axis_law(Ly, even_y, 0.0)
+    thx = sum(Wx[c] * c * c for c in Wx)  # axis temperature: second moment at rest
+    jplus = sum(cy * Wy[cy] for cy in Wy if cy > 0)
+    Fbot, Ftop = axis_law(Lx, even_x, wall_u[0]), axis_law(Lx, even_x, wall_u[1])
     f = dict(f0)
     for _ in range(steps):
         post = {}
@@ -52,7 +77,7 @@ def run(dims, Lx, Ly, nx, ny, omega, g, bc_x, bc_y, wall_u, end_rho, f0, steps):
                 rho = sum(f[(x, y, cx, cy)] for cx, cy in vel)
                 ux = sum(f[(x, y, cx, cy)] * cx for cx, cy in vel) / rho
                 uy = sum(f[(x, y, cx, cy)] * cy for cx, cy in vel) / rho
-                ex, ey = dice_law(Lx, ux), dice_law(Ly, uy)
+                ex, ey = axis_law(Lx, even_x, ux), axis_law(Ly, even_y, uy)
                 for cx, cy in vel:
                     v = f[(x, y, cx, cy)]
                     feq = rho * ex[cx] * ey[cy]
@@ -93,23 +118,27 @@ def run(dims, Lx, Ly, nx, ny, omega, g, bc_x, bc_y, wall_u, end_rho, f0, steps):
     return f
 
 
-def to_dict(arr, Lx, Ly):
-    """[q][y][x] array (q = b*(2Lx+1) + a) -> dict keyed by (x, y, cx, cy)."""
+def to_dict(arr, Lx, Ly, even_x=False, even_y=False):
+    """[q][y][x] array (q = b*Qx + a, velocities in increasing order per axis)
+    -> dict keyed by (x, y, cx, cy)."""
+    vx, vy = axis_velocities(Lx, even_x), axis_velocities(Ly, even_y)
     Q, ny, nx = arr.shape
     out = {}
     for q in range(Q):
-        b, a = divmod(q, 2 * Lx + 1)
+        b, a = divmod(q, len(vx))
         for y in range(ny):
             for x in range(nx):
-                out[(x, y, a - Lx, b - Ly)] = float(arr[q, y, x])
+                out[(x, y, vx[a], vy[b])] = float(arr[q, y, x])
     return out
 
 
-def from_dict(d, Lx, Ly, nx, ny):
+def from_dict(d, Lx, Ly, nx, ny, even_x=False, even_y=False):
     import numpy as np
 
-    Qx, Qy = 2 * Lx + 1, 2 * Ly + 1
-    arr = np.zeros((Qx * Qy, ny, nx))
+    vx, vy = axis_velocities(Lx, even_x), axis_velocities(Ly, even_y)
+    ix = {c: i for i, c in enumerate(vx)}
+    iy = {c: i for i, c in enumerate(vy)}
+    arr = np.zeros((len(vx) * len(vy), ny, nx))
     for (x, y, cx, cy), v in d.items():
-        arr[(cy + Ly) * Qx + (cx + Lx), y, x] = v
+        arr[iy[cy] * len(vx) + ix[cx], y, x] = v
     return arr
