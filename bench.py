@@ -61,16 +61,22 @@ def time_steps(solver, steps: int, warmup: int):
     return start.elapsed_time(stop) / 1e3, wall
 
 
-def run_gpu(level: int, nx: int, ny: int, storage: str, steps: int, warmup: int):
+def run_gpu(level: int, nx: int, ny: int, storage: str, steps: int, warmup: int, lattice: str = "odd"):
+    """lattice: "odd" G-D1Q(2N+1) on both axes, "even" G-D1Q(2N+2) on both,
+    "mixed_even" D1Q3 along the channel x G-D1Q(2N+2) across it."""
     from paper_1905_04597_amd import glbm
     from paper_1905_04597_amd import workloads as wl
 
     w = wl.poiseuille(nx=nx, ny=ny, level=level, storage=storage)
+    if lattice == "even":
+        w.even_x = w.even_y = True
+    elif lattice == "mixed_even":
+        w.level_x, w.even_y = 1, True
     s = glbm.solver_for(w)
     s.init_fields()
     gpu_s, wall_s = time_steps(s, steps, warmup)
     nodes = nx * ny
-    Q = (2 * level + 1) ** 2
+    Q = w.nvel
     per_step = gpu_s / steps
     algo_bytes = 2 * Q * ELEM_BYTES[storage] * nodes
     out = {
@@ -302,9 +308,18 @@ def main(argv=None):
         sweep = []
         for lv in range(1, 8):
             r = run_gpu(lv, a.nx, a.ny, a.storage, a.sweep_steps, 5)
-            sweep.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
-                          if k in ("k", "Q", "glups", "achieved_GBs", "ms_per_step")})
+            sweep.append({"lattice": "odd", "N": lv})
+            sweep[-1].update({k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
+                              if k in ("k", "Q", "glups", "achieved_GBs", "ms_per_step")})
             sweep[-1]["frac"] = round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)
+        # the G-D1Q(2N+2) lattices: D1Q3 x G-D1Q(2N+2) channels and the
+        # symmetric products
+        for lattice, levels in (("mixed_even", range(1, 8)), ("even", range(1, 7))):
+            for lv in levels:
+                r = run_gpu(lv, a.nx, a.ny, a.storage, a.sweep_steps, 5, lattice)
+                sweep.append({"lattice": lattice, "N": lv, "Q": r["Q"], "glups": round(r["glups"], 4),
+                              "achieved_GBs": round(r["achieved_GBs"], 4), "ms_per_step": round(r["ms_per_step"], 4),
+                              "frac": round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)})
     batched = None if a.no_batched else run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)
     served = None if a.no_served else run_served(a.served_seconds)
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.level)

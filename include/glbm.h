@@ -68,21 +68,34 @@ extern "C" {
 /* Largest hierarchy level per axis built into the library. */
 #define GLBM_MAX_LEVEL 7
 
+/* Velocity set of an axis (section 2). */
+#define GLBM_AXIS_ODD 0  /* G-D1Q(2N+1): velocities -N..N, theta = N/3 (unit lattice step) */
+#define GLBM_AXIS_EVEN 1 /* G-D1Q(2N+2), zero velocity removed (Eqs. maineq01_noball-
+                            maineq04_noball): velocities (n + 1/2) c on a grid of half the
+                            lattice step c, i.e. the odd integers -(2N+1)..2N+1 in grid
+                            units, theta = (4N+3)/3 (Eq. temp_2N2 with c = 2 grid units).
+                            Built: one dimension (N = 1..7), the mixed lattices
+                            G-D1Q3 x G-D1Q(2N+2) with walls across the even axis (the form of
+                            sections 5.3-5.4, N = 1..7) and the symmetric two-dimensional
+                            products (N = 1..6). */
+
 typedef struct glbm_config {
     int32_t dims;     /* 1 or 2 */
-    int32_t level_x;  /* hierarchy level N of the x axis: 2N+1 velocities, 1..GLBM_MAX_LEVEL */
+    int32_t level_x;  /* hierarchy level N of the x axis, 1..GLBM_MAX_LEVEL */
     int32_t level_y;  /* level of the y axis (two dimensions), 1..GLBM_MAX_LEVEL; ignored in 1D */
     int32_t storage;  /* GLBM_STORE_* */
     int64_t nx, ny;   /* nodes per axis; ny is ignored (1) in one dimension */
     double tau;       /* relaxation time (> 0), or <= 0 to derive it from kn */
     double kn;        /* Knudsen number of Eq. kn: tau = kn H / sqrt(2 theta), with
-                         H = ny and theta = level_y / 3 in two dimensions (walls half
-                         way between nodes), H = nx and theta = level_x / 3 in one */
+                         H = ny and theta of the y axis in two dimensions (walls half
+                         way between nodes), H = nx and theta of the x axis in one */
     int32_t bc_x;     /* GLBM_BC_PERIODIC or GLBM_BC_EQ_ENDS */
     int32_t bc_y;     /* GLBM_BC_PERIODIC or GLBM_BC_WALL (two dimensions) */
     double wall_u[2]; /* x velocity of the bottom (y = -1/2) and top (y = ny - 1/2) walls */
     double end_rho[2];/* densities of the left (x < 0) and right (x >= nx) equilibrium ends */
     double g;         /* body force along x: momentum added per node and step */
+    int32_t kind_x;   /* GLBM_AXIS_ODD or GLBM_AXIS_EVEN */
+    int32_t kind_y;   /* GLBM_AXIS_ODD or GLBM_AXIS_EVEN (two dimensions); ignored in 1D */
 } glbm_config;
 
 /* Global diagnostics, FP64 sums over all nodes (glbm_stats). */
@@ -97,7 +110,8 @@ typedef struct glbm_stats {
     double wall_mass[2];    /* mass absorbed (and re-emitted) by the bottom/top wall in the
                                streaming from t to t+1 */
     double wall_momentum[2];/* x momentum given to the bottom/top wall in that streaming */
-    double nonpositive_nodes; /* nodes with |u| above sqrt(2 N theta) on some axis
+    double nonpositive_nodes; /* nodes with u^2 above 2 N theta0 on some axis (theta0 of the
+                                 underlying 2N+1 walk: N/3, or 4N/3 on an even axis's half grid)
                                  (equilibrium not positive, section 3) */
 } glbm_stats_t;
 

@@ -2,8 +2,8 @@
 
 Usage: python -m paper_1905_04597_amd.build [--jobs J] [--incremental]
 
-Every hierarchy level and row layout is compiled as its own object (they
-are the slow part), in parallel, and linked into
+Every (axis kind, row layout, hierarchy level) is compiled as its own object
+(they are the slow part), in parallel, and linked into
 ``paper_1905_04597_amd/libglbm.so``.
 """
 from __future__ import annotations
@@ -64,10 +64,12 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     os.makedirs(BUILD, exist_ok=True)
     tasks = [(os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), [])]
     for lv in LEVELS:
-        for compact in (0, 1):
-            tasks.append((os.path.join(CSRC, "glbm_inst.hip"),
-                          os.path.join(BUILD, "glbm_inst_%d%s.o" % (lv, "c" if compact else "")),
-                          ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_COMPACT=%d" % compact]))
+        for even in (0, 1):
+            for compact in (0, 1):
+                tasks.append((os.path.join(CSRC, "glbm_inst.hip"),
+                              os.path.join(BUILD, "glbm_inst_%s%d%s.o" % ("e" if even else "", lv,
+                                                                         "c" if compact else "")),
+                              ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_EVEN=%d" % even, "-DGLBM_COMPACT=%d" % compact]))
     todo = [t for t in tasks if not incremental or _stale(t[0], t[1])]
     jobs = jobs or min(len(todo) or 1, os.cpu_count() or 4, 16)
     if todo:

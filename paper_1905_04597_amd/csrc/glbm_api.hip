@@ -36,32 +36,20 @@ int hip_fail(hipError_t e, const char *what)
     return fail(GLBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-Variant g_variants[kMaxLevel + 1][kMaxLevel + 1][4][3][2];
+Variant g_variants[kAxisCodes][kAxisCodes][4][3][2];
 std::once_flag g_once;
 
 void register_all()
 {
-    register_level_1();
-    register_level_2();
-    register_level_3();
-    register_level_4();
-    register_level_5();
-    register_level_6();
-    register_level_7();
-    register_mixed();
-    register_compact_1();
-    register_compact_2();
-    register_compact_3();
-    register_compact_4();
-    register_compact_5();
-    register_compact_6();
-    register_compact_7();
-    register_compact_mixed();
+#define GLBM_CALL_REGISTER(E, C, L) register_##E##_##C##_##L();
+    GLBM_OBJECTS(GLBM_CALL_REGISTER)
+#undef GLBM_CALL_REGISTER
 }
 
 // Host copy of the per-axis equilibrium at rho = 1 (N-fold convolution of the
-// D1Q3 equilibrium at u/N, lattice units), in double, for the wall tables.
-void host_axis_equilibrium(int N, double u, double *F)
+// D1Q3 equilibrium at u/N, lattice units), in double, for the wall tables;
+// the 2N+2 axis averages neighbouring pairs of the 2N+1 one at u/2.
+void host_odd_equilibrium(int N, double u, double *F)
 {
     double cur[kMaxQ1] = {1.0};
     int len = 1;
@@ -82,8 +70,40 @@ void host_axis_equilibrium(int N, double u, double *F)
     for (int i = 0; i < 2 * N + 1; ++i) F[i] = cur[i];
 }
 
+// Axis of code A (see Axis in glbm_device.h): velocities, reach, temperature.
+struct HostAxis {
+    int code, N, q, vmax;
+    bool even;
+    double theta;
+};
+
+HostAxis host_axis(int N, bool even)
+{
+    HostAxis a;
+    a.N = N;
+    a.even = even;
+    a.code = N == 0 ? 0 : even ? kEven + N : N;
+    a.q = N == 0 ? 1 : even ? 2 * N + 2 : 2 * N + 1;
+    a.vmax = even ? 2 * N + 1 : N;
+    a.theta = even ? (4.0 * N + 3.0) / 3.0 : N / 3.0;
+    return a;
+}
+
+void host_axis_equilibrium(const HostAxis &ax, double u, double *F)
+{
+    if (!ax.even) {
+        host_odd_equilibrium(ax.N, u, F);
+        return;
+    }
+    double G[kMaxQ1];
+    host_odd_equilibrium(ax.N, 0.5 * u, G);
+    for (int a = 0; a <= 2 * ax.N + 1; ++a)
+        F[a] = 0.5 * ((a >= 1 ? G[a - 1] : 0.0) + (a <= 2 * ax.N ? G[a] : 0.0));
+}
+
 struct Geometry {
-    int lx, ly, q, eb;
+    HostAxis x, y;
+    int q, eb;
     int bcx;  // kernel variant's x boundary and row layout (BcX)
     int64_t nx, ny, nxp;
     uint64_t plane_bytes, buf_bytes;
@@ -96,6 +116,10 @@ int check_config(const glbm_config *c, Geometry *g)
     const int lx = c->level_x, ly = c->dims == 2 ? c->level_y : 0;
     if (lx < 1 || lx > kMaxLevel) return fail(GLBM_ERR_INVALID, "level_x must be in 1..%d", kMaxLevel);
     if (c->dims == 2 && (ly < 1 || ly > kMaxLevel)) return fail(GLBM_ERR_INVALID, "level_y must be in 1..%d", kMaxLevel);
+    const int kx = c->kind_x, ky = c->dims == 2 ? c->kind_y : GLBM_AXIS_ODD;
+    if ((kx != GLBM_AXIS_ODD && kx != GLBM_AXIS_EVEN) || (ky != GLBM_AXIS_ODD && ky != GLBM_AXIS_EVEN))
+        return fail(GLBM_ERR_INVALID, "axis kinds must be GLBM_AXIS_ODD or GLBM_AXIS_EVEN");
+    const HostAxis ax = host_axis(lx, kx == GLBM_AXIS_EVEN), ay = host_axis(ly, ky == GLBM_AXIS_EVEN);
     if (c->storage < GLBM_STORE_F32 || c->storage > GLBM_STORE_BF16_SHIFTED_SR)
         return fail(GLBM_ERR_INVALID, "unknown storage %d", c->storage);
     const int64_t nx = c->nx, ny = c->dims == 2 ? c->ny : 1;
@@ -107,15 +131,19 @@ int check_config(const glbm_config *c, Geometry *g)
         return fail(GLBM_ERR_INVALID, "bc_y must be periodic or wall");
     if (c->bc_x == GLBM_BC_EQ_ENDS && bcy == GLBM_BC_WALL)
         return fail(GLBM_ERR_INVALID, "walls and equilibrium ends cannot be combined");
-    if (bcy == GLBM_BC_WALL && ny < 2 * ly)
-        return fail(GLBM_ERR_INVALID, "ny (%lld) must be at least 2*level_y with walls", (long long)ny);
-    if (c->dims == 2 && bcy == GLBM_BC_PERIODIC && ny < ly)
-        return fail(GLBM_ERR_INVALID, "periodic ny (%lld) must be at least level_y", (long long)ny);
-    if (c->bc_x == GLBM_BC_EQ_ENDS && nx < lx)
-        return fail(GLBM_ERR_INVALID, "nx must be at least level_x with equilibrium ends");
-    g->lx = lx;
-    g->ly = ly;
-    g->q = (2 * lx + 1) * (2 * ly + 1);
+    // no population may cross both walls (or wrap more than once across y) in
+    // one step
+    if (bcy == GLBM_BC_WALL && ny < 2 * ay.vmax)
+        return fail(GLBM_ERR_INVALID, "ny (%lld) must be at least 2*%d (twice the fastest y velocity) with walls",
+                    (long long)ny, ay.vmax);
+    if (c->dims == 2 && bcy == GLBM_BC_PERIODIC && ny < ay.vmax)
+        return fail(GLBM_ERR_INVALID, "periodic ny (%lld) must be at least the fastest y velocity %d", (long long)ny,
+                    ay.vmax);
+    if (c->bc_x == GLBM_BC_EQ_ENDS && nx < ax.vmax)
+        return fail(GLBM_ERR_INVALID, "nx must be at least the fastest x velocity with equilibrium ends");
+    g->x = ax;
+    g->y = ay;
+    g->q = ax.q * ay.q;
     g->eb = (c->storage == GLBM_STORE_BF16_SHIFTED || c->storage == GLBM_STORE_BF16_SHIFTED_SR) ? 2 : 4;
     g->nx = nx;
     g->ny = ny;
@@ -123,7 +151,7 @@ int check_config(const glbm_config *c, Geometry *g)
     // column x); otherwise padded rows with ghosts (node x at column kGhost + x)
     const bool compact = c->dims == 2 && c->bc_x == GLBM_BC_PERIODIC && nx < kCompactBelow;
     g->bcx = compact ? BCX_WRAP : c->bc_x == GLBM_BC_EQ_ENDS ? BCX_EQ : BCX_PERIODIC;
-    g->nxp = compact ? nx : (kGhost + nx + lx + 63) / 64 * 64;
+    g->nxp = compact ? nx : (kGhost + nx + ax.vmax + 63) / 64 * 64;
     g->plane_bytes = ((uint64_t)(ny * g->nxp) * g->eb + 255) & ~(uint64_t)255;
     g->buf_bytes = (g->plane_bytes * g->q + 255) & ~(uint64_t)255;
     if (nx * ny > (int64_t)0x7fffffff / 4) return fail(GLBM_ERR_INVALID, "too many nodes");
@@ -154,9 +182,9 @@ __global__ void reduce_partials(const double *partials, int nblocks, double *out
 }  // namespace
 
 namespace glbm {
-Variant *variant_slot(int lx, int ly, int storage, int bcx, int bcy)
+Variant *variant_slot(int ax, int ay, int storage, int bcx, int bcy)
 {
-    return &g_variants[lx][ly][storage][bcx][bcy];
+    return &g_variants[ax][ay][storage][bcx][bcy];
 }
 }  // namespace glbm
 
@@ -201,7 +229,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     double tau = cfg->tau;
     if (!(tau > 0.0)) {
         const double H = cfg->dims == 2 ? (double)g.ny : (double)g.nx;
-        const double theta = (cfg->dims == 2 ? g.ly : g.lx) / 3.0;
+        const double theta = cfg->dims == 2 ? g.y.theta : g.x.theta;
         if (!(cfg->kn > 0.0)) return fail(GLBM_ERR_INVALID, "either tau > 0 or kn > 0 is required");
         tau = cfg->kn * H / sqrt(2.0 * theta);  // Eq. kn with nu = theta tau
     }
@@ -210,9 +238,10 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
 
     std::call_once(g_once, register_all);
     const int bcy = cfg->dims == 2 ? cfg->bc_y : GLBM_BC_PERIODIC;
-    const Variant *v = variant_slot(g.lx, g.ly, cfg->storage, g.bcx, bcy);
+    const Variant *v = variant_slot(g.x.code, g.y.code, cfg->storage, g.bcx, bcy);
     if (!v->step)
-        return fail(GLBM_ERR_UNSUPPORTED, "no kernels built for levels (%d, %d) with these boundaries", g.lx, g.ly);
+        return fail(GLBM_ERR_UNSUPPORTED, "no kernels built for axes (%s%d, %s%d) with these boundaries",
+                    g.x.even ? "even " : "", g.x.N, g.y.even ? "even " : "", g.y.N);
 
     glbm_solver *h = new (std::nothrow) glbm_solver();
     if (!h) return fail(GLBM_ERR_INVALID, "out of host memory");
@@ -242,7 +271,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     a.nodes = (int32_t)nodes;
     a.remap = 1;
     a.omega = (float)omega;
-    a.gth = (float)(cfg->g / (g.lx / 3.0));  // force shape W_a c_a g / theta_x
+    a.gth = (float)(cfg->g / g.x.theta);  // force shape W_a c_a g / theta_x
     a.g = (float)cfg->g;
     // wall emission: unit-density equilibrium at the wall speed (x) times the
     // rest weights (y), in FP32; the kernels divide the absorbed mass by the
@@ -250,9 +279,9 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     double F[kMaxQ1];
     for (int side = 0; side < 2; ++side) {
         const double U = bcy == GLBM_BC_WALL ? cfg->wall_u[side] : 0.0;
-        host_axis_equilibrium(g.lx, U, F);
+        host_axis_equilibrium(g.x, U, F);
         double sum = 0.0;
-        for (int i = 0; i < 2 * g.lx + 1; ++i) {
+        for (int i = 0; i < g.x.q; ++i) {
             a.fw[side][i] = (float)F[i];
             sum += (double)a.fw[side][i];
         }
@@ -274,7 +303,7 @@ static int do_init(glbm_t *h, const float *rho, const float *ux, const float *uy
     if (h->cfg.bc_x == GLBM_BC_EQ_ENDS) {
         a.dst = h->buf[0];
         a.dst2 = h->buf[1];
-        const int n = h->geo.q * (int)h->geo.ny * 2 * h->geo.lx;
+        const int n = h->geo.q * (int)h->geo.ny * 2 * h->geo.x.vmax;
         e = h->var->ends(a, (n + kBlock - 1) / kBlock, (float)h->cfg.end_rho[0], (float)h->cfg.end_rho[1], h->stream);
         if (e != hipSuccess) return hip_fail(e, "launching the end-state fill");
     }
@@ -548,7 +577,7 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
             for (int i = 0; i < n; ++i) {
                 const glbm_solver *m = members[i];
                 if (m->var != v) continue;
-                const int64_t nx = m->geo.nx, ny = m->geo.ny, ly = m->geo.ly;
+                const int64_t nx = m->geo.nx, ny = m->geo.ny, ly = m->geo.y.vmax;  // rows with wall emission
                 const int64_t cnt = rows == ROWS_ALL ? nx * ny : rows == ROWS_INTERIOR ? (ny - 2 * ly) * nx : 2 * ly * nx;
                 if (cnt > 0) parts.push_back({i, (int)cnt, (double)cnt * m->geo.q});
             }

@@ -11,8 +11,8 @@
 // Memory layout of a population buffer: velocity planes [q][y][xp] with rows
 // of nxp padded columns (a multiple of 64); node x lives at column x + G,
 // G = 64, so that a wave of 64 nodes reads and writes whole, aligned cache
-// lines of its own row.  The LX columns on each side of the interior are
-// ghosts.  With periodic x every store of an edge node is replicated into the
+// lines of its own row.  The columns within reach of the fastest x velocity
+// on each side of the interior are ghosts.  With periodic x every store of an edge node is replicated into the
 // matching ghost columns, so a pull never wraps: the source of velocity c_x
 // sits at a constant byte shift from the node, which the buffer loads take as
 // an immediate offset.  With fixed equilibrium ends the ghosts hold the end
@@ -37,7 +37,7 @@
 namespace glbm {
 
 constexpr int kMaxLevel = 7;
-constexpr int kMaxQ1 = 2 * kMaxLevel + 1;
+constexpr int kMaxQ1 = 2 * kMaxLevel + 2;  // velocities of the largest axis
 constexpr int kBlock = 256;
 constexpr int kNumStats = 11;
 constexpr int kGhost = 64;  // padded column of node x = 0 (>= the largest level)
@@ -50,16 +50,45 @@ enum StorageKind { ST_F32 = 0, ST_F32S = 1, ST_BF16S = 2, ST_BF16SR = 3 };
 enum BcX { BCX_PERIODIC = 0, BCX_WRAP = 1, BCX_EQ = 2 };
 enum BcY { BCY_PERIODIC = 0, BCY_WALL = 1 };
 
+// ------------------------------------------------------------------ axes
+// An axis is named by a code A.  A = N (1..7): the G-D1Q(2N+1) axis of level
+// N, velocities -N..N, temperature N/3 (section 2 with unit lattice step).
+// A = kEven + N: the G-D1Q(2N+2) axis of level N with the zero velocity
+// removed (section 2, Eqs. maineq01_noball-maineq04_noball): its velocities
+// (n + 1/2) c are laid on a grid of half the lattice step c, so they are the
+// odd integers -(2N+1)..2N+1, and its temperature is (4N+3) c^2 / 12 =
+// (4N+3)/3 (Eq. temp_2N2 with c = 2).  A = 0: the absent y axis of a
+// one-dimensional lattice (the single velocity 0).
+constexpr int kEven = 8;
+constexpr int kAxisCodes = 2 * kEven;
+
+template <int A>
+struct Axis {
+    static constexpr bool even = A > kEven;
+    static constexpr int N = even ? A - kEven : A;
+    static constexpr int Q = A == 0 ? 1 : even ? 2 * N + 2 : 2 * N + 1;
+    static constexpr int vmax = even ? 2 * N + 1 : N;  // largest |c|: rows or columns one step reaches
+    static constexpr int cmin = even ? 1 : 0;          // smallest |c|
+    static constexpr int c(int a) { return even ? 2 * a - (2 * N + 1) : a - N; }
+    static constexpr double theta = even ? (4.0 * N + 3.0) / 3.0 : N / 3.0;
+    // positivity (section 3): the underlying 2N+1 walk keeps P0 >= 0 while
+    // u^2 <= 2 N theta0, theta0 = N s^2 / 3 for its lattice step s (1, or 2
+    // on the half grid of an even axis)
+    static constexpr double u2max = 2.0 * N * N / 3.0 * (even ? 4.0 : 1.0);
+};
+
 // ---------------------------------------------------------------- tables
-// Rest weights of a level-N axis: the equilibrium at rho = 1, u = 0, i.e.
+// Rest weights of an axis: the equilibrium at rho = 1, u = 0.  Level N:
 // the coefficients of (1/6 z^-1 + 2/3 + 1/6 z)^N (N-fold sum of D1Q3 at
-// rest, section 2 and Appendix A), computed in double at compile time and
-// made exactly symmetric.
-template <int N>
+// rest, section 2 and Appendix A); the 2N+2 axis takes half of each
+// neighbouring pair of those.  Computed in double at compile time and made
+// exactly symmetric.
+template <int A>
 struct RestWeights {
-    double w[2 * N + 1];
+    double w[Axis<A>::Q];
     constexpr RestWeights() : w{}
     {
+        constexpr int N = Axis<A>::N;
         double cur[2 * kMaxLevel + 1] = {};
         cur[0] = 1.0;
         int len = 1;
@@ -73,19 +102,26 @@ struct RestWeights {
             len += 2;
             for (int i = 0; i < len; ++i) cur[i] = nxt[i];
         }
-        for (int i = 0; i <= N; ++i) w[i] = w[2 * N - i] = cur[i];
+        for (int i = 0; i < N; ++i) cur[2 * N - i] = cur[i];
+        if constexpr (Axis<A>::even) {
+            for (int a = 0; a <= 2 * N + 1; ++a)
+                w[a] = 0.5 * ((a >= 1 ? cur[a - 1] : 0.0) + (a <= 2 * N ? cur[a] : 0.0));
+        } else {
+            for (int a = 0; a <= 2 * N; ++a) w[a] = cur[a];
+        }
     }
 };
 
-template <int N>
-inline constexpr RestWeights<N> kRest{};
+template <int A>
+inline constexpr RestWeights<A> kRest{};
 
-// Half flux J+ = sum_{n>0} n W_n of the FP32-rounded rest weights (exact sum).
-template <int N>
+// Half flux J+ = sum_{c>0} c W_c of the FP32-rounded rest weights (exact sum).
+template <int A>
 constexpr double half_flux_f32()
 {
     double s = 0.0;
-    for (int n = 1; n <= N; ++n) s += n * (double)(float)kRest<N>.w[N + n];
+    for (int a = 0; a < Axis<A>::Q; ++a)
+        if (Axis<A>::c(a) > 0) s += Axis<A>::c(a) * (double)(float)kRest<A>.w[a];
     return s;
 }
 
@@ -99,30 +135,40 @@ constexpr double kGrid = 16777216.0;  // 2^24
 
 constexpr long long snap(double w) { return (long long)(w * kGrid + 0.5); }
 
-// Shift of the shifted storages: S_ab ~ W_a W_b on the grid, symmetric,
-// summing exactly to 1; plus the moments of S that the kernels add back.
+// Shift of the shifted storages: S_ab ~ W_a W_b on the grid, symmetric; the
+// rounding remainder goes to the slowest populations (|c_x|, |c_y| smallest:
+// 1, 2 or 4 of them) in equal parts, so the sum is exactly 1 when the
+// remainder divides evenly (always with a zero velocity on both axes) and
+// otherwise 1 - r 2^-24 (r < 4), which FP32 holds exactly: rho = sum +
+// sum of deviations.  Plus the moments of S that the kernels add back.
 template <int LX, int LY>
 struct ShiftTable {
-    static constexpr int QX = 2 * LX + 1, QY = 2 * LY + 1;
+    static constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q;
     float s[QY][QX];
+    float sum;             // sum of S
     float sxx, syy;        // sum S c_x^2, sum S c_y^2
     float absorbed;        // sum of S over the populations one wall absorbs per column
-    constexpr ShiftTable() : s{}, sxx(0.0f), syy(0.0f), absorbed(0.0f)
+    constexpr ShiftTable() : s{}, sum(0.0f), sxx(0.0f), syy(0.0f), absorbed(0.0f)
     {
         long long q[QY][QX] = {};
         long long tot = 0;
         for (int b = 0; b < QY; ++b)
             for (int a = 0; a < QX; ++a) tot += (q[b][a] = snap(kRest<LX>.w[a] * kRest<LY>.w[b]));
-        q[LY][LX] += (long long)kGrid - tot;
-        long long xx = 0, yy = 0, ab = 0;
+        const long long m = (Axis<LX>::even ? 2 : 1) * (Axis<LY>::even ? 2 : 1);
+        const long long rem = (long long)kGrid - tot;
+        const long long share = rem >= 0 ? rem / m : -((-rem + m - 1) / m);  // floor(rem / m)
+        long long all = 0, xx = 0, yy = 0, ab = 0;
         for (int b = 0; b < QY; ++b)
             for (int a = 0; a < QX; ++a) {
-                const long long ca = a - LX, cb = b - LY;
+                const long long ca = Axis<LX>::c(a), cb = Axis<LY>::c(b);
+                if ((ca < 0 ? -ca : ca) == Axis<LX>::cmin && (cb < 0 ? -cb : cb) == Axis<LY>::cmin) q[b][a] += share;
+                all += q[b][a];
                 xx += q[b][a] * ca * ca;
                 yy += q[b][a] * cb * cb;
                 if (cb < 0) ab += q[b][a] * (-cb);
                 s[b][a] = (float)(q[b][a] / kGrid);
             }
+        sum = (float)(all / kGrid);
         sxx = (float)(xx / kGrid);
         syy = (float)(yy / kGrid);
         absorbed = (float)(ab / kGrid);
@@ -297,7 +343,7 @@ __device__ __forceinline__ int tile_index(const KArgs &p)
 // i.e. of the step probabilities of Eq. maineq04 with c = 1, theta = N/3:
 // p+- = 1/6 +- v/2 + v^2/2 and p0 = 1 - p+ - p-.
 template <int N, class T = float>
-__device__ __forceinline__ void axis_equilibrium(T u, T (&F)[2 * N + 1])
+__device__ __forceinline__ void odd_equilibrium(T u, T (&F)[2 * N + 1])
 {
     if constexpr (N == 0) {
         F[0] = T(1);
@@ -327,23 +373,45 @@ __device__ __forceinline__ void axis_equilibrium(T u, T (&F)[2 * N + 1])
     }
 }
 
+// Equilibrium of axis A at rho = 1.  The 2N+2 axis (half grid, c = 2): the
+// 2N+1 equilibrium of lattice step 2 at u, which is the unit-step one at
+// u / 2, each velocity (n + 1/2) c taking half of its two neighbours n c and
+// (n + 1) c (Eqs. maineq01_noball-maineq04_noball).
+template <int A, class T = float>
+__device__ __forceinline__ void axis_equilibrium(T u, T (&F)[Axis<A>::Q])
+{
+    constexpr int N = Axis<A>::N;
+    if constexpr (!Axis<A>::even) {
+        odd_equilibrium<N, T>(u, F);
+    } else {
+        T G[2 * N + 1];
+        odd_equilibrium<N, T>(T(0.5) * u, G);
+        F[0] = T(0.5) * G[0];
+        unroll<2 * N>([&](auto J) {
+            constexpr int j = J + 1;
+            F[j] = T(0.5) * (G[j - 1] + G[j]);
+        });
+        F[2 * N + 1] = T(0.5) * G[2 * N];
+    }
+}
+
 // ------------------------------------------------------------ the pull
 // Working value of a population: f itself (plain storage) or its deviation
 // f - S_ab from the rest state (shifted storage).
 template <int LX, int LY, int ST>
 struct Lat {
-    static constexpr int QX = 2 * LX + 1, QY = 2 * LY + 1, Q = QX * QY;
+    static constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q, Q = QX * QY;
     static constexpr int EB = Elem<ST>::bytes;
     static constexpr bool shifted = Elem<ST>::shifted;
 };
 
 // Byte offsets of the x sources of node x within a row (see the layouts
-// above).  Padded rows: the source of velocity index a (c_x = a - LX) is
-// column G + x - c_x, a constant shift that the load takes as an immediate.
-// Compact rows: column (x - c_x) mod nx, one register per velocity.
+// above).  Padded rows: the source of velocity index a is column G + x - c_x,
+// a constant shift that the load takes as an immediate.  Compact rows: column
+// (x - c_x) mod nx, one register per velocity.
 template <int LX, int EB, int BCX>
 struct XAddr {
-    static constexpr int QX = 2 * LX + 1;
+    static constexpr int QX = Axis<LX>::Q, V = Axis<LX>::vmax;
     static constexpr bool compact = BCX == BCX_WRAP;
     uint32_t col[compact ? QX : 1];
     uint32_t self;
@@ -351,7 +419,7 @@ struct XAddr {
     {
         if constexpr (compact) {
             unroll<QX>([&](auto A) {
-                constexpr int ca = (int)A - LX;
+                constexpr int ca = Axis<LX>::c(A);
                 int c = x - ca;
                 if constexpr (ca > 0)
                     while (c < 0) c += nx;
@@ -361,7 +429,7 @@ struct XAddr {
             });
             self = (uint32_t)x * (uint32_t)EB;
         } else {
-            col[0] = (uint32_t)(x + kGhost - LX) * (uint32_t)EB;
+            col[0] = (uint32_t)(x + kGhost - V) * (uint32_t)EB;
             self = (uint32_t)(x + kGhost) * (uint32_t)EB;
         }
     }
@@ -372,7 +440,7 @@ struct XAddr {
         if constexpr (compact)
             return rowb + col[a];
         else
-            return rowb + col[0] + (uint32_t)((2 * LX - a) * EB);
+            return rowb + col[0] + (uint32_t)((V - Axis<LX>::c(a)) * EB);
     }
     __device__ __forceinline__ uint32_t own(uint32_t rowb) const { return rowb + self; }
 };
@@ -397,14 +465,14 @@ __device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, const 
     using L = Lat<LX, LY, ST>;
     float s = 0.0f, m = 0.0f;
     unroll<L::QY>([&](auto B) {
-        constexpr int b = B, cb = b - LY;
+        constexpr int b = B, cb = Axis<LY>::c(b);
         if constexpr ((BOTTOM && cb < 0) || (!BOTTOM && cb > 0)) {
             constexpr int depth = cb < 0 ? -cb : cb;
             unroll<depth>([&](auto R) {
                 const int row = BOTTOM ? (int)R : p.ny - 1 - (int)R;
                 const uint32_t rowb = row_bytes<L::EB>(p, row);
                 unroll<L::QX>([&](auto A) {
-                    constexpr int a = A, ca = a - LX;
+                    constexpr int a = A, ca = Axis<LX>::c(a);
                     const float v = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)(b * L::QX + a) * p.plane_bytes);
                     s += v;
                     if (mom) m = __builtin_fmaf((float)ca, v, m);
@@ -421,19 +489,20 @@ __device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, const 
 // source buffer, or emitted by a wall where the source row is outside.
 template <int LX, int LY, int ST, int BCX, int BCY>
 __device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
-                                     float (&v)[2 * LY + 1][2 * LX + 1])
+                                     float (&v)[Axis<LY>::Q][Axis<LX>::Q])
 {
     using L = Lat<LX, LY, ST>;
     float rw[2] = {0.0f, 0.0f};
     if constexpr (BCY == BCY_WALL) {
         // the mass the FP32 emission tables give out per unit wall density
         constexpr double jp = half_flux_f32<LY>();
-        if (y < LY) rw[0] = wall_absorbed<LX, LY, ST, BCX, true>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[0]);
-        if (y >= p.ny - LY)
+        constexpr int reach = Axis<LY>::vmax;  // rows that take wall emission
+        if (y < reach) rw[0] = wall_absorbed<LX, LY, ST, BCX, true>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[0]);
+        if (y >= p.ny - reach)
             rw[1] = wall_absorbed<LX, LY, ST, BCX, false>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[1]);
     }
     unroll<L::QY>([&](auto B) {
-        constexpr int b = B, cb = b - LY;
+        constexpr int b = B, cb = Axis<LY>::c(b);
         int ys = y - cb;
         bool emit = false;
         if constexpr (BCY == BCY_WALL) {
@@ -466,7 +535,7 @@ __device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, 
 // Populations of one node in registers, one FP32 value each.
 template <int LX, int LY>
 struct FloatRegs {
-    float (&v)[2 * LY + 1][2 * LX + 1];
+    float (&v)[Axis<LY>::Q][Axis<LX>::Q];
     template <int b, int a>
     __device__ __forceinline__ float get() const { return v[b][a]; }
     template <int b, int a>
@@ -479,7 +548,7 @@ struct FloatRegs {
 // storage does, so the stores are exact.
 template <int LX, int LY, int ST>
 struct PackedRegs {
-    static constexpr int QX = 2 * LX + 1, Q = QX * (2 * LY + 1), NP = (Q + 1) / 2;
+    static constexpr int QX = Axis<LX>::Q, Q = QX * Axis<LY>::Q, NP = (Q + 1) / 2;
     uint32_t (&pk)[NP];
     uint32_t h;  // node hash for the stochastic rounding
     template <int b, int a>
@@ -514,10 +583,10 @@ __device__ __forceinline__ void density_velocity(const Regs &v, float &rho, floa
     jx = 0.0f;
     jy = 0.0f;
     unroll<L::QY>([&](auto B) {
-        constexpr int b = B, cb = b - LY;
+        constexpr int b = B, cb = Axis<LY>::c(b);
         float rs = 0.0f, rx = 0.0f;
         unroll<L::QX>([&](auto A) {
-            constexpr int a = A, ca = a - LX;
+            constexpr int a = A, ca = Axis<LX>::c(a);
             const float f = v.template get<b, a>();
             rs += f;
             if constexpr (ca != 0) rx = __builtin_fmaf((float)ca, f, rx);
@@ -526,7 +595,7 @@ __device__ __forceinline__ void density_velocity(const Regs &v, float &rho, floa
         jx += rx;
         if constexpr (cb != 0) jy = __builtin_fmaf((float)cb, rs, jy);
     });
-    rho = L::shifted ? 1.0f + r : r;
+    rho = L::shifted ? kShift<LX, LY>.sum + r : r;
     const float inv = 1.0f / rho;
     ux = jx * inv;
     uy = jy * inv;
@@ -540,7 +609,9 @@ __device__ __forceinline__ void density_velocity(const Regs &v, float &rho, floa
 // deterministically in u, which a channel flow (u constant along rows) would
 // integrate into a drift over thousands of steps.  The exact (FP64) sums of
 // the FP32 tables give that defect, and it is taken out of the equilibrium of
-// the rest population (mass) and of the +-1 populations (momentum).
+// the slowest populations (mass: the rest population, or the symmetric set of
+// smallest |c| on axes without one) and of the c = +-1 populations among them
+// (momentum).
 template <int LX, int LY, int ST, class Regs>
 __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, float jx, float jy, float ux, float uy)
 {
@@ -554,7 +625,7 @@ __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, floa
         double Fd[L::QX];
         axis_equilibrium<LX, double>((double)ux, Fd);
         unroll<L::QX>([&](auto A) {
-            constexpr int a = A, ca = a - LX;
+            constexpr int a = A, ca = Axis<LX>::c(a);
             rF[a] = (float)((double)rho * Fd[a]);
             sx += (double)rF[a];
             mx += (double)ca * (double)rF[a];
@@ -565,7 +636,7 @@ __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, floa
         double Fd[L::QY];
         axis_equilibrium<LY, double>((double)uy, Fd);
         unroll<L::QY>([&](auto B) {
-            constexpr int b = B, cb = b - LY;
+            constexpr int b = B, cb = Axis<LY>::c(b);
             Fy[b] = (float)Fd[b];
             sy += (double)Fy[b];
             my += (double)cb * (double)Fy[b];
@@ -573,24 +644,29 @@ __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, floa
     }
     // sum f^eq = sx sy, sum f^eq c_x = mx sy, sum f^eq c_y = sx my (exactly, for
     // the products of the FP32 tables)
-    const float dm = (float)(sx * sy - (double)rho);
-    const float hx = (float)(0.5 * (mx * sy - (double)jx));
-    const float hy = (float)(0.5 * (sx * my - (double)jy));
+    // spread over the mx (my) populations of smallest |c_x| (|c_y|): powers of
+    // two, so the shares are exact
+    constexpr int nx_min = Axis<LX>::cmin ? 2 : 1, ny_min = Axis<LY>::cmin ? 2 : 1;
+    const float dm = (float)(sx * sy - (double)rho) * (1.0f / (nx_min * ny_min));
+    const float hx = (float)(0.5 * (mx * sy - (double)jx)) * (1.0f / ny_min);
+    const float hy = (float)(0.5 * (sx * my - (double)jy)) * (1.0f / nx_min);
     unroll<L::QY>([&](auto B) {
-        constexpr int b = B, cb = b - LY;
+        constexpr int b = B, cb = Axis<LY>::c(b);
+        constexpr bool ymin = (cb < 0 ? -cb : cb) == Axis<LY>::cmin;
         unroll<L::QX>([&](auto A) {
-            constexpr int a = A, ca = a - LX;
+            constexpr int a = A, ca = Axis<LX>::c(a);
+            constexpr bool xmin = (ca < 0 ? -ca : ca) == Axis<LX>::cmin;
             const float f = v.template get<b, a>();
             float neq;  // f^eq - f
             if constexpr (L::shifted)
                 neq = __builtin_fmaf(rF[a], Fy[b], -kShift<LX, LY>.s[b][a]) - f;
             else
                 neq = __builtin_fmaf(rF[a], Fy[b], -f);
-            if constexpr (ca == 0 && cb == 0) neq -= dm;
-            if constexpr (cb == 0 && ca == 1) neq -= hx;
-            if constexpr (cb == 0 && ca == -1) neq += hx;
-            if constexpr (ca == 0 && cb == 1) neq -= hy;
-            if constexpr (ca == 0 && cb == -1) neq += hy;
+            if constexpr (xmin && ymin) neq -= dm;
+            if constexpr (ymin && ca == 1) neq -= hx;
+            if constexpr (ymin && ca == -1) neq += hx;
+            if constexpr (xmin && cb == 1) neq -= hy;
+            if constexpr (xmin && cb == -1) neq += hy;
             v.template put<b, a>(__builtin_fmaf(gK[a], (float)kRest<LY>.w[b], __builtin_fmaf(om, neq, f)));
         });
     });
@@ -600,15 +676,16 @@ __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, floa
 // ghost columns when x is periodic.  `h` seeds the stochastic rounding.
 template <int LX, int LY, int ST, int BCX>
 __device__ __forceinline__ void store_node(const KArgs &p, rsrc_t rd, int x, int y,
-                                           const float (&v)[2 * LY + 1][2 * LX + 1], uint32_t h)
+                                           const float (&v)[Axis<LY>::Q][Axis<LX>::Q], uint32_t h)
 {
     using L = Lat<LX, LY, ST>;
+    constexpr int V = Axis<LX>::vmax;
     // columns holding node x: its own, and with periodic padded rows every
-    // column of [G - LX, G + nx + LX) congruent to it modulo nx
+    // column of [G - V, G + nx + V) congruent to it modulo nx
     int pc = x + kGhost;
     if constexpr (BCX == BCX_WRAP) pc = x;
-    if constexpr (BCX == BCX_PERIODIC) pc = kGhost - LX + (x + LX) % p.nx;
-    for (; pc < kGhost + p.nx + LX; pc += p.nx) {
+    if constexpr (BCX == BCX_PERIODIC) pc = kGhost - V + (x + V) % p.nx;
+    for (; pc < kGhost + p.nx + V; pc += p.nx) {
         const uint32_t off = (uint32_t)(y * p.nxp + pc) * (uint32_t)L::EB;
         unroll<L::QY>([&](auto B) {
             unroll<L::QX>([&](auto A) {
@@ -651,7 +728,7 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
     const XAddr<LX, 2, BCX> xa(x, p.nx);
     uint32_t pk[P::NP];
     unroll<L::QY>([&](auto B) {
-        constexpr int b = B, cb = b - LY;
+        constexpr int b = B, cb = Axis<LY>::c(b);
         int ys = y - cb;
         if constexpr (BCY != BCY_WALL) {
             if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
@@ -672,10 +749,11 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
     float rho, jx, jy, ux, uy;
     density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
     collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
+    constexpr int V = Axis<LX>::vmax;
     int pc = x + kGhost;
     if constexpr (BCX == BCX_WRAP) pc = x;
-    if constexpr (BCX == BCX_PERIODIC) pc = kGhost - LX + (x + LX) % p.nx;
-    for (; pc < kGhost + p.nx + LX; pc += p.nx) {
+    if constexpr (BCX == BCX_PERIODIC) pc = kGhost - V + (x + V) % p.nx;
+    for (; pc < kGhost + p.nx + V; pc += p.nx) {
         const uint32_t off = (uint32_t)(y * p.nxp + pc) * 2u;
         unroll<L::Q>([&](auto Qi) {
             constexpr int q = Qi;
@@ -687,7 +765,8 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
 }
 
 // Rows a step launch covers: all of them, the rows that take no wall
-// emission, or the LY rows next to each wall.
+// emission, or the rows next to each wall that take it (as many as the
+// fastest y velocity reaches).
 enum StepRows { ROWS_ALL = 0, ROWS_INTERIOR = 1, ROWS_WALLS = 2 };
 
 // One time step of node i: pull from f*(t-1), collide, write f*(t).  With
@@ -722,13 +801,14 @@ __device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
 template <int LY, int ROWS>
 __device__ __forceinline__ int row_set_node(int i, int nx, int ny)
 {
+    constexpr int R = Axis<LY>::vmax;
     if constexpr (ROWS == ROWS_ALL) {
         return i < nx * ny ? i : -1;
     } else if constexpr (ROWS == ROWS_INTERIOR) {
-        return i < (ny - 2 * LY) * nx ? i + LY * nx : -1;
+        return i < (ny - 2 * R) * nx ? i + R * nx : -1;
     } else {
-        if (i >= 2 * LY * nx) return -1;
-        return i < LY * nx ? i : i + (ny - 2 * LY) * nx;
+        if (i >= 2 * R * nx) return -1;
+        return i < R * nx ? i : i + (ny - 2 * R) * nx;
     }
 }
 
@@ -795,14 +875,14 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(KArgs p)
     double r = 0.0, jx = 0.0, jy = 0.0;
     unroll<L::QY>([&](auto B) {
         unroll<L::QX>([&](auto A) {
-            constexpr int a = A, b = B, ca = a - LX, cb = b - LY;
+            constexpr int a = A, b = B, ca = Axis<LX>::c(a), cb = Axis<LY>::c(b);
             const double f = v[b][a];
             r += f;
             jx += ca * f;
             jy += cb * f;
         });
     });
-    const double rho = L::shifted ? 1.0 + r : r;
+    const double rho = L::shifted ? (double)kShift<LX, LY>.sum + r : r;
     const double ux = jx / rho, uy = jy / rho;
     // second moments from f - f^eq: the product equilibrium has
     // sum f^eq c_x^2 = rho (u_x^2 + theta_x) and sum f^eq c_x c_y = rho u_x u_y,
@@ -814,7 +894,7 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(KArgs p)
     double e2 = 0.0, exy = 0.0;
     unroll<L::QY>([&](auto B) {
         unroll<L::QX>([&](auto A) {
-            constexpr int a = A, b = B, ca = a - LX, cb = b - LY;
+            constexpr int a = A, b = B, ca = Axis<LX>::c(a), cb = Axis<LY>::c(b);
             double f = v[b][a];
             if constexpr (L::shifted) f += (double)kShift<LX, LY>.s[b][a];
             const double dev = f - rho * Fx[a] * Fy[b];
@@ -826,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(KArgs p)
     if (p.o_rho) p.o_rho[i] = (float)rho;
     if (p.o_ux) p.o_ux[i] = (float)ux;
     if (p.o_uy) p.o_uy[i] = (float)uy;
-    if (p.o_T) p.o_T[i] = (float)(((LX + LY) / 3.0 + e2 / rho) / dims);
+    if (p.o_T) p.o_T[i] = (float)((Axis<LX>::theta + Axis<LY>::theta + e2 / rho) / dims);
     if (p.o_pxy) p.o_pxy[i] = (float)exy;
     if (p.o_f) {
         unroll<L::QY>([&](auto B) {
@@ -908,14 +988,15 @@ __global__ __launch_bounds__(kBlock) void ends_kernel(KArgs p, float rho_left, f
 {
     using L = Lat<LX, LY, ST>;
     const int i = blockIdx.x * kBlock + (int)threadIdx.x;
-    const int per_row = 2 * LX;
+    constexpr int V = Axis<LX>::vmax;
+    const int per_row = 2 * V;
     if (i >= L::Q * p.ny * per_row) return;
     const int q = i / (p.ny * per_row);
     const int rem = i - q * p.ny * per_row;
     const int y = rem / per_row, k = rem - y * per_row;
-    const bool left = k < LX;
-    // k in [0, LX): columns G-LX .. G-1; k in [LX, 2LX): columns G+nx .. G+nx+LX-1
-    const int pc = left ? kGhost - LX + k : kGhost + p.nx + (k - LX);
+    const bool left = k < V;
+    // k in [0, V): columns G-V .. G-1; k in [V, 2V): columns G+nx .. G+nx+V-1
+    const int pc = left ? kGhost - V + k : kGhost + p.nx + (k - V);
     const int a = q % L::QX, b = q / L::QX;
     double w = 1.0, s = 0.0;
     // run-time index into compile-time tables
@@ -955,7 +1036,7 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
         double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
         unroll<L::QY>([&](auto B) {
             unroll<L::QX>([&](auto A) {
-                constexpr int a = A, b = B, ca = a - LX, cb = b - LY;
+                constexpr int a = A, b = B, ca = Axis<LX>::c(a), cb = Axis<LY>::c(b);
                 const double f = ld<ST>(rs, base, (uint32_t)(b * L::QX + a) * p.plane_bytes);
                 r += f;
                 jx += ca * f;
@@ -964,7 +1045,7 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
             });
         });
         if constexpr (L::shifted) {
-            r += 1.0;
+            r += (double)kShift<LX, LY>.sum;
             e += (double)kShift<LX, LY>.sxx + (double)kShift<LX, LY>.syy;
         }
         // f*(t) carries the force momentum g of step t's collision
@@ -980,19 +1061,18 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
             double r0 = 0.0, j0 = 0.0;
             unroll<L::QY>([&](auto B) {
                 unroll<L::QX>([&](auto A) {
-                    constexpr int a = A, b = B, ca = a - LX;
+                    constexpr int a = A, b = B, ca = Axis<LX>::c(a);
                     const double f = ld<ST>(rp, base, (uint32_t)(b * L::QX + a) * p.plane_bytes);
                     r0 += f;
                     j0 += ca * f;
                 });
             });
-            if constexpr (L::shifted) r0 += 1.0;
+            if constexpr (L::shifted) r0 += (double)kShift<LX, LY>.sum;
             const double d = ux - (j0 - p.g) / r0;
             acc[5] = d * d;
         }
-        // positivity domain of section 3: |u| <= sqrt(2 N theta) = N sqrt(2/3)
-        const double lim = 2.0 / 3.0;
-        if (ux * ux > lim * LX * LX || (LY > 0 && uy * uy > lim * LY * LY)) acc[10] = 1.0;
+        // positivity domain of section 3 (Axis::u2max)
+        if (ux * ux > Axis<LX>::u2max || (LY > 0 && uy * uy > Axis<LY>::u2max)) acc[10] = 1.0;
         if constexpr (BCY == BCY_WALL) {
             if (y == 0) {
                 float m;

@@ -1,8 +1,9 @@
 // Kernel instantiations for one hierarchy level, selected at compile time
-// with -DGLBM_LEVEL=N (N = 1..7); -DGLBM_LEVEL=0 builds the mixed-level
-// lattices.  -DGLBM_COMPACT=1 builds the compact-row variants of the 2D
-// periodic-x lattices instead (narrow lattices).  Each (level, layout) is its
-// own object file so the build runs in parallel.
+// with -DGLBM_LEVEL=N (N = 1..7); -DGLBM_LEVEL=0 builds the mixed lattices.
+// -DGLBM_EVEN=1 builds the lattices of G-D1Q(2N+2) axes instead of
+// G-D1Q(2N+1) ones; -DGLBM_COMPACT=1 the compact-row variants of the 2D
+// periodic-x lattices (narrow lattices).  Each (axis kind, layout, level) is
+// its own object file so the build runs in parallel.
 #include "glbm_internal.h"
 
 namespace glbm {
@@ -14,7 +15,8 @@ struct Launchers {
     {
         if constexpr (Elem<ST>::bytes == 2 && BCY == BCY_WALL) {
             // packed interior rows, then the rows next to the walls
-            const int interior = (a.ny - 2 * LY) * a.nx, walls = 2 * LY * a.nx;
+            constexpr int R = Axis<LY>::vmax;  // rows next to each wall that take emission
+            const int interior = (a.ny - 2 * R) * a.nx, walls = 2 * R * a.nx;
             if (interior > 0)
                 hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>),
                                    dim3((interior + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
@@ -85,50 +87,61 @@ void add_all_storages()
 
 #define GLBM_CAT2(a, b) a##b
 #define GLBM_CAT(a, b) GLBM_CAT2(a, b)
+#define GLBM_REG3(E, C, L) register_##E##_##C##_##L
+#define GLBM_REG(E, C, L) GLBM_REG3(E, C, L)
 
-#if GLBM_COMPACT
-// Two dimensions with periodic x in compact rows: the same lattices as the
-// padded 2D variants below.
-#if GLBM_LEVEL >= 1
-void GLBM_CAT(register_compact_, GLBM_LEVEL)()
-{
-    constexpr int N = GLBM_LEVEL;
-    add_all_storages<N, N, BCX_WRAP, BCY_PERIODIC>();
-    add_all_storages<N, N, BCX_WRAP, BCY_WALL>();
-}
+// Axis codes of this object: the G-D1Q(2N+1) axis of level N, or the
+// G-D1Q(2N+2) one (code kEven + N).
+#if GLBM_EVEN
+#define GLBM_AX(N) (kEven + (N))
 #else
-void register_compact_mixed()
-{
-    add_all_storages<1, 2, BCX_WRAP, BCY_WALL>();
-    add_all_storages<1, 3, BCX_WRAP, BCY_WALL>();
-    add_all_storages<1, 4, BCX_WRAP, BCY_WALL>();
-    add_all_storages<1, 5, BCX_WRAP, BCY_WALL>();
-    add_all_storages<1, 6, BCX_WRAP, BCY_WALL>();
-    add_all_storages<1, 7, BCX_WRAP, BCY_WALL>();
-}
+#define GLBM_AX(N) (N)
 #endif
-#elif GLBM_LEVEL >= 1
-void GLBM_CAT(register_level_, GLBM_LEVEL)()
+
+#if GLBM_LEVEL >= 1
+void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, GLBM_LEVEL)()
 {
-    constexpr int N = GLBM_LEVEL;
+    constexpr int N = GLBM_LEVEL, A = GLBM_AX(GLBM_LEVEL);
+#if GLBM_COMPACT
+    // two dimensions, periodic x in compact rows (narrow lattices)
+    if constexpr (!GLBM_EVEN || N <= 6) {
+        add_all_storages<A, A, BCX_WRAP, BCY_PERIODIC>();
+        add_all_storages<A, A, BCX_WRAP, BCY_WALL>();
+    }
+#else
     // one dimension: periodic or fixed equilibrium ends
-    add_all_storages<N, 0, BCX_PERIODIC, BCY_PERIODIC>();
-    add_all_storages<N, 0, BCX_EQ, BCY_PERIODIC>();
-    // two dimensions, same level on both axes: periodic or walls across y
-    add_all_storages<N, N, BCX_PERIODIC, BCY_PERIODIC>();
-    add_all_storages<N, N, BCX_PERIODIC, BCY_WALL>();
+    add_all_storages<A, 0, BCX_PERIODIC, BCY_PERIODIC>();
+    add_all_storages<A, 0, BCX_EQ, BCY_PERIODIC>();
+    // two dimensions, the same axis twice: periodic or walls across y (the
+    // symmetric even lattices up to N = 6: (2N+2)^2 <= 196 velocities)
+    if constexpr (!GLBM_EVEN || N <= 6) {
+        add_all_storages<A, A, BCX_PERIODIC, BCY_PERIODIC>();
+        add_all_storages<A, A, BCX_PERIODIC, BCY_WALL>();
+    }
+#endif
+    (void)N;
 }
 #else
-// Mixed lattices G-D1Q3 (streamwise x) x G-D1Q(2N+1) (across the walls), the
-// form the channel flows of sections 5.3-5.4 use.
-void register_mixed()
+// Mixed lattices D1Q3 (streamwise x) x G-D1Q(2N+1) or G-D1Q(2N+2) (across the
+// walls), the form the channel flows of sections 5.3-5.4 use.
+void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, 0)()
 {
-    add_all_storages<1, 2, BCX_PERIODIC, BCY_WALL>();
-    add_all_storages<1, 3, BCX_PERIODIC, BCY_WALL>();
-    add_all_storages<1, 4, BCX_PERIODIC, BCY_WALL>();
-    add_all_storages<1, 5, BCX_PERIODIC, BCY_WALL>();
-    add_all_storages<1, 6, BCX_PERIODIC, BCY_WALL>();
-    add_all_storages<1, 7, BCX_PERIODIC, BCY_WALL>();
+#if GLBM_COMPACT
+    constexpr int BX = BCX_WRAP;
+#else
+    constexpr int BX = BCX_PERIODIC;
+#endif
+#if !GLBM_EVEN
+    add_all_storages<1, 2, BX, BCY_WALL>();
+#else
+    add_all_storages<1, GLBM_AX(1), BX, BCY_WALL>();
+    add_all_storages<1, GLBM_AX(2), BX, BCY_WALL>();
+#endif
+    add_all_storages<1, GLBM_AX(3), BX, BCY_WALL>();
+    add_all_storages<1, GLBM_AX(4), BX, BCY_WALL>();
+    add_all_storages<1, GLBM_AX(5), BX, BCY_WALL>();
+    add_all_storages<1, GLBM_AX(6), BX, BCY_WALL>();
+    add_all_storages<1, GLBM_AX(7), BX, BCY_WALL>();
 }
 #endif
 

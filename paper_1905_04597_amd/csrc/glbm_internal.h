@@ -26,25 +26,20 @@ struct Variant {
     bool split_rows = false;  // steps run as interior rows + wall rows (16-bit storage with walls)
 };
 
-// Registry of built variants, indexed by levels (0..kMaxLevel), storage, bc_x, bc_y.
-Variant *variant_slot(int lx, int ly, int storage, int bcx, int bcy);
+// Registry of built variants, indexed by axis codes (see Axis), storage, bc_x
+// (with the row layout), bc_y.
+Variant *variant_slot(int ax, int ay, int storage, int bcx, int bcy);
 
-// Defined once per built level in glbm_inst.hip.
-void register_level_1();
-void register_level_2();
-void register_level_3();
-void register_level_4();
-void register_level_5();
-void register_level_6();
-void register_level_7();
-void register_mixed();
-void register_compact_1();
-void register_compact_2();
-void register_compact_3();
-void register_compact_4();
-void register_compact_5();
-void register_compact_6();
-void register_compact_7();
-void register_compact_mixed();
+// One registration function per object file of glbm_inst.hip,
+// register_E_C_L(): E = 1 for the lattices with G-D1Q(2N+2) axes, C = 1 for
+// the compact-row variants, L = level (0: the mixed lattices with a D1Q3
+// x axis).
+#define GLBM_OBJECTS(X)                                                                                        \
+    X(0, 0, 0) X(0, 0, 1) X(0, 0, 2) X(0, 0, 3) X(0, 0, 4) X(0, 0, 5) X(0, 0, 6) X(0, 0, 7)                   \
+    X(0, 1, 0) X(0, 1, 1) X(0, 1, 2) X(0, 1, 3) X(0, 1, 4) X(0, 1, 5) X(0, 1, 6) X(0, 1, 7)                   \
+    X(1, 0, 0) X(1, 0, 1) X(1, 0, 2) X(1, 0, 3) X(1, 0, 4) X(1, 0, 5) X(1, 0, 6) X(1, 0, 7)                   \
+    X(1, 1, 0) X(1, 1, 1) X(1, 1, 2) X(1, 1, 3) X(1, 1, 4) X(1, 1, 5) X(1, 1, 6) X(1, 1, 7)
+#define GLBM_DECLARE_REGISTER(E, C, L) void register_##E##_##C##_##L();
+GLBM_OBJECTS(GLBM_DECLARE_REGISTER)
 
 }  // namespace glbm

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libglbm.so")
 
 OK = 0
 BC = {"periodic": 0, "wall": 1, "eq_ends": 2}
+AXIS_ODD, AXIS_EVEN = 0, 1
 STORAGE = {"f32": 0, "f32_shifted": 1, "bf16_shifted": 2, "bf16_shifted_sr": 3}
 MAX_LEVEL = 7
 
@@ -48,6 +49,8 @@ class Config(ctypes.Structure):
         ("wall_u", ctypes.c_double * 2),
         ("end_rho", ctypes.c_double * 2),
         ("g", ctypes.c_double),
+        ("kind_x", ctypes.c_int32),
+        ("kind_y", ctypes.c_int32),
     ]
 
 
@@ -120,7 +123,9 @@ def _check(rc: int, what: str):
 
 
 def make_config(dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0, bc_x="periodic", bc_y="periodic",
-                wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0, storage="f32") -> Config:
+                wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0, storage="f32", even_x=False, even_y=False) -> Config:
+    """even_x / even_y select the G-D1Q(2N+2) velocity set (zero velocity
+    removed) for that axis instead of G-D1Q(2N+1)."""
     c = Config()
     c.dims = int(dims)
     c.level_x = int(level_x)
@@ -135,12 +140,14 @@ def make_config(dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0, bc_x="per
     c.wall_u[0], c.wall_u[1] = float(wall_u[0]), float(wall_u[1])
     c.end_rho[0], c.end_rho[1] = float(end_rho[0]), float(end_rho[1])
     c.g = float(g)
+    c.kind_x = AXIS_EVEN if even_x else AXIS_ODD
+    c.kind_y = AXIS_EVEN if even_y else AXIS_ODD
     return c
 
 
 def config_from_workload(w) -> Config:
     return make_config(w.dims, w.level_x, w.level_y, w.nx, w.ny, w.tau, w.kn, w.bc_x, w.bc_y,
-                       w.wall_u, w.end_rho, w.g, w.storage)
+                       w.wall_u, w.end_rho, w.g, w.storage, getattr(w, "even_x", False), getattr(w, "even_y", False))
 
 
 def population_bytes(cfg: Config) -> int:
@@ -181,7 +188,9 @@ class Solver:
         self.ny = int(cfg.ny) if cfg.dims == 2 else 1
         self.level_x = int(cfg.level_x)
         self.level_y = int(cfg.level_y) if cfg.dims == 2 else 0
-        self.Q = (2 * self.level_x + 1) * (2 * self.level_y + 1)
+        qx = 2 * self.level_x + (2 if cfg.kind_x == AXIS_EVEN else 1)
+        qy = 1 if cfg.dims == 1 else 2 * self.level_y + (2 if cfg.kind_y == AXIS_EVEN else 1)
+        self.Q = qx * qy
         self._keep = []
 
     # ------------------------------------------------------------- helpers

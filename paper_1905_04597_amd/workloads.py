@@ -36,10 +36,14 @@ class Workload:
     steps: int = 0
     storage: str = "f32"    # f32 | f32_shifted | bf16_shifted
     init: str = "rest"      # rest | sod | fields | populations
+    even_x: bool = False    # G-D1Q(2N+2) velocity set on x (zero velocity removed)
+    even_y: bool = False    # ... on y
 
     @property
     def nvel(self) -> int:
-        return (2 * self.level_x + 1) * (2 * self.level_y + 1)
+        qx = 2 * self.level_x + (2 if self.even_x else 1)
+        qy = 1 if self.dims == 1 else 2 * self.level_y + (2 if self.even_y else 1)
+        return qx * qy
 
     @property
     def nodes(self) -> int:

@@ -38,13 +38,15 @@ def make_pair(params: dict, storage: str):
     """Oracle and GPU solvers for the same configuration."""
     p = dict(params)
     dims = p["dims"]
+    ex, ey = p.get("even_x", False), p.get("even_y", False)
     orc = oracle.OracleSolver(dims, p["level_x"], p.get("level_y", 0), p["nx"], p.get("ny", 1),
                               tau=p.get("tau", 0.0), kn=p.get("kn", 0.0),
                               bc_x=ORACLE_BC[p.get("bc_x", "periodic")], bc_y=ORACLE_BC[p.get("bc_y", "periodic")],
-                              wall_u=p.get("wall_u", (0, 0)), end_rho=p.get("end_rho", (1, 1)), g=p.get("g", 0.0))
+                              wall_u=p.get("wall_u", (0, 0)), end_rho=p.get("end_rho", (1, 1)), g=p.get("g", 0.0),
+                              even_x=ex, even_y=ey)
     cfg = glbm.make_config(dims, p["level_x"], p.get("level_y", 0), p["nx"], p.get("ny", 1), p.get("tau", 0.0),
                            p.get("kn", 0.0), p.get("bc_x", "periodic"), p.get("bc_y", "periodic"),
-                           p.get("wall_u", (0, 0)), p.get("end_rho", (1, 1)), p.get("g", 0.0), storage)
+                           p.get("wall_u", (0, 0)), p.get("end_rho", (1, 1)), p.get("g", 0.0), storage, ex, ey)
     gpu = glbm.Solver(cfg)
     return orc, gpu
 

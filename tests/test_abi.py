@@ -57,20 +57,35 @@ def test_population_bytes_layout():
     assert glbm.population_bytes(c) == 169 * ((100 * 63 * 2 + 255) // 256 * 256)
     c = glbm.make_config(2, 6, 6, 64, 100, tau=0.8, storage="bf16_shifted_sr")
     assert glbm.population_bytes(c) == 169 * 100 * nxp(64, 6) * 2
+    # G-D1Q(2N+2) axes: 2N+2 velocities, ghosts as deep as the fastest one (2N+1)
+    c = glbm.make_config(1, 3, 0, 500, 1, kn=0.01, bc_x="eq_ends", even_x=True)
+    assert glbm.population_bytes(c) == 8 * nxp(500, 7) * 4
+    c = glbm.make_config(2, 1, 3, 4, 41, kn=0.1, bc_y="wall", even_y=True, storage="f32_shifted")
+    assert glbm.population_bytes(c) == 3 * 8 * ((41 * 4 * 4 + 255) // 256 * 256)
 
 
 @pytest.mark.parametrize("kwargs,needle", [
     (dict(dims=3, level_x=1), "dims"),
     (dict(dims=1, level_x=0, nx=10), "level_x"),
     (dict(dims=1, level_x=8, nx=10), "level_x"),
-    (dict(dims=2, level_x=3, level_y=3, nx=4, ny=5, bc_y="wall"), "2*level_y"),
+    (dict(dims=2, level_x=3, level_y=3, nx=4, ny=5, bc_y="wall"), "fastest y velocity"),
     (dict(dims=2, level_x=2, level_y=2, nx=4, ny=8, bc_x="eq_ends", bc_y="wall"), "combined"),
     (dict(dims=2, level_x=7, level_y=7, nx=8192, ny=4096, bc_y="wall"), "4 GiB"),
+    # the even axis reaches 2N+1 rows: ny >= 2 (2N+1) with walls
+    (dict(dims=2, level_x=1, level_y=3, nx=4, ny=13, bc_y="wall", even_y=True), "fastest y velocity"),
+    (dict(dims=2, level_x=1, level_y=3, nx=4, ny=6, even_y=True), "periodic ny"),
 ])
 def test_invalid_configs_are_rejected(kwargs, needle):
     c = glbm.make_config(**kwargs)
     assert glbm.load().glbm_population_bytes(ctypes.byref(c)) == 0
     assert needle in glbm.load().glbm_last_error().decode()
+
+
+def test_axis_kind_is_validated():
+    c = glbm.make_config(2, 2, 2, 8, 8, tau=0.8)
+    c.kind_y = 5
+    assert glbm.load().glbm_population_bytes(ctypes.byref(c)) == 0
+    assert "axis kinds" in glbm.load().glbm_last_error().decode()
 
 
 def test_create_rejects_missing_buffers_without_touching_the_gpu():

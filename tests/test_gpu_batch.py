@@ -28,6 +28,9 @@ MEMBERS = [
     dict(dims=1, level_x=3, nx=300, kn=0.01, bc_x="eq_ends", end_rho=(1.0, 0.125), storage="f32_shifted"),
     dict(dims=2, level_x=1, level_y=4, nx=50, ny=30, kn=0.1, bc_y="wall", wall_u=(0.0, 0.04), storage="f32_shifted"),
     dict(dims=2, level_x=3, level_y=3, nx=4, ny=37, kn=0.05, bc_y="wall", wall_u=(-0.03, 0.05), storage="f32_shifted"),
+    dict(dims=2, level_x=1, level_y=3, even_y=True, nx=4, ny=41, kn=0.2, bc_y="wall", wall_u=(-0.03, 0.05),
+         storage="bf16_shifted_sr"),
+    dict(dims=2, level_x=1, level_y=2, even_y=True, nx=80, ny=23, kn=0.5, bc_y="wall", g=1e-5, storage="f32_shifted"),
 ]
 
 
@@ -102,7 +105,7 @@ def test_batch_update_joins_and_leaves_bitwise():
     stream = torch.cuda.Stream()
     # the batch runs on its own stream: hand the members over through a sync
     torch.cuda.synchronize()
-    schedule = [([0, 1, 2], 7), ([1, 2, 3, 4, 5], 5), ([5, 6, 7, 8], 9), ([0, 8], 4), (list(range(9)), 6)]
+    schedule = [([0, 1, 2, 9], 7), ([1, 2, 3, 4, 5, 10], 5), ([5, 6, 7, 8], 9), ([0, 8, 9], 4), (list(range(11)), 6)]
     steps = [0] * len(MEMBERS)
     b = None
     for members, k in schedule:

@@ -12,7 +12,10 @@ are covered, and x-uniform channels are compared bitwise across them.
 
 Which storage meets which bound (tests/gpu_common.py BOUND): FP32 deviation
 storage (f - S, the FP32 path) meets 1e-5 on every case.  Plain FP32 keeps
-f ~ W and re-rounds it every step and is held to 5e-5.  BF16 deviation
+f ~ W and re-rounds it every step and is held to 5e-5 on the lattices it is
+run on here (its error grows with the number and speed of the velocities:
+1.3e-4 on the symmetric G-D2Q196 case, which therefore runs the FP32 path
+only).  BF16 deviation
 storage with stochastic rounding is checked on smooth near-rest flows against
 its measured per-node bound (8 significand bits).
 """
@@ -59,13 +62,35 @@ CASES = {
                                    wall_u=(-0.05, 0.05), g=1e-4), "wave", 50, F32),
     "d2q49_nx2_wrap": (dict(dims=2, level_x=3, level_y=3, nx=2, ny=9, tau=0.9, g=1e-4), "populations", 20, F32),
     "d2q81_periodic_wave_nx16": (dict(dims=2, level_x=4, level_y=4, nx=16, ny=40, tau=1.5), "wave", 100, ALL),
+    # G-D1Q(2N+2) axes (zero velocity removed; odd velocities on the half grid)
+    "even_d1q6_periodic_fields": (dict(dims=1, level_x=2, even_x=True, nx=301, tau=0.7, g=1e-4), "fields", 20,
+                                  ("f32_shifted",)),
+    "even_d1q8_ends_sod": (dict(dims=1, level_x=3, even_x=True, nx=500, kn=0.01, bc_x="eq_ends",
+                                end_rho=(1.0, 0.125)), "sod", 300, F32),
+    "even_d1q4_nx2_wrap": (dict(dims=1, level_x=1, even_x=True, nx=2, tau=0.9), "populations", 20, F32),
+    "mixed_d1q3xd1q6_couette_nx4": (dict(dims=2, level_x=1, level_y=2, even_y=True, nx=4, ny=64, kn=0.1,
+                                         bc_y="wall", wall_u=(-0.05, 0.05)), "rest", 400, ALL),
+    "mixed_d1q3xd1q8_walls_wave": (dict(dims=2, level_x=1, level_y=3, even_y=True, nx=70, ny=40, tau=0.9,
+                                        bc_y="wall", wall_u=(0.03, -0.02), g=5e-5), "wave", 100, ALL),
+    "mixed_d1q3xd1q16_walls_fields": (dict(dims=2, level_x=1, level_y=7, even_y=True, nx=9, ny=40, kn=0.3,
+                                           bc_y="wall", wall_u=(-0.04, 0.04)), "fields", 20, F32),
+    "even_d2q36_periodic_force_pops": (dict(dims=2, level_x=2, level_y=2, even_x=True, even_y=True, nx=67, ny=13,
+                                            tau=0.8, g=2e-4), "populations", 10, F32),
+    "even_d2q64_walls_nx5": (dict(dims=2, level_x=3, level_y=3, even_x=True, even_y=True, nx=5, ny=20, tau=1.1,
+                                  bc_y="wall", wall_u=(0.05, -0.03)), "fields", 10, F32),
+    "even_d2q196_walls_fields": (dict(dims=2, level_x=6, level_y=6, even_x=True, even_y=True, nx=70, ny=28,
+                                      tau=0.65, bc_y="wall", wall_u=(-0.03, 0.03), g=2e-5), "fields", 5,
+                                 ("f32_shifted",)),
 }
 
 PARAMS = [(name, st) for name, (_, _, _, sts) in CASES.items() for st in sts]
 
 
 def theta_of(params):
-    return max(params["level_x"], params.get("level_y", 0)) / 3.0
+    def th(n, even):
+        return (4 * n + 3) / 3.0 if even else n / 3.0
+    return max(th(params["level_x"], params.get("even_x", False)),
+               th(params.get("level_y", 0), params.get("even_y", False)))
 
 
 @pytest.mark.parametrize("name,storage", PARAMS, ids=["%s-%s" % p for p in PARAMS])
