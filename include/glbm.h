@@ -193,6 +193,9 @@ typedef struct glbm_batch_options {
     int32_t tile_nodes;  /* nodes per workgroup: 64, 128 or 256 (0 = 256) */
     int32_t order;       /* GLBM_ORDER_* */
     int32_t graph_steps; /* steps per captured HIP graph; 0 = plain launches */
+    int32_t resident_nodes; /* members of at most this many nodes are stepped by one
+                               workgroup each, all steps of a chunk in one launch per
+                               variant (small lattices: no launch per step); 0 = none */
 } glbm_batch_options;
 
 typedef struct glbm_batch glbm_batch_t;

@@ -13,6 +13,9 @@ choices shape the schedule:
   the accelerator's dies), or contiguous by decreasing work.
 * ``graph_steps`` - steps per captured graph (0 = plain launches): graphs
   remove the host cost of one launch per variant and step.
+* ``resident_nodes`` - members up to this size are stepped by one workgroup
+  each, every step of a chunk in one launch (a per-instance schedule: small
+  lattices leave the per-step launches).
 
 :func:`autotune` times every candidate on scratch copies of the members
 (fresh lattices of the same configurations, initialised at rest) and
@@ -28,10 +31,12 @@ from . import glbm
 TILE_NODES = (64, 128, 256)
 ORDERS = ("member", "interleave", "largest_first")
 GRAPH_STEPS = (0, 32)
+RESIDENT_NODES = (0, 8192)
 
 
-def candidates(tiles=TILE_NODES, orders=ORDERS, graphs=GRAPH_STEPS):
-    return [dict(tile_nodes=t, order=o, graph_steps=g) for t, o, g in itertools.product(tiles, orders, graphs)]
+def candidates(tiles=TILE_NODES, orders=ORDERS, graphs=GRAPH_STEPS, resident=RESIDENT_NODES):
+    return [dict(tile_nodes=t, order=o, graph_steps=g, resident_nodes=r)
+            for t, o, g, r in itertools.product(tiles, orders, graphs, resident)]
 
 
 def time_batch(solvers, options: dict, steps: int, warmup: int = 2) -> float:

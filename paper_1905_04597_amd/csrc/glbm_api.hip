@@ -460,7 +460,8 @@ int glbm_destroy(glbm_t *h)
 //
 // All device tables of a batch live in one allocation, uploaded from a
 // pinned host copy with one asynchronous copy on the batch's stream:
-//   [step counter int64][phase int32 x n][t0 int64 x n][args KArgs x 2n][tiles]
+//   [step counter int64][phase int32 x n][t0 int64 x n][args KArgs x 2n]
+//   [tiles of each (variant, row set)][resident member lists of each variant]
 // Re-planning (glbm_batch_update) rewrites them in place; the allocation
 // grows (by doubling) only when a plan does not fit.
 
@@ -472,8 +473,14 @@ struct glbm_batch {
         int ntiles;
     };
     glbm_batch_options opt;
+    struct ResidentSet {
+        const Variant *var;
+        size_t list;     // byte offset of the member indices in the table block
+        int count;
+    };
     std::vector<glbm_solver *> members;
     std::vector<RowSet> sets;
+    std::vector<ResidentSet> resident;
     hipStream_t user;  // caller's stream (may be NULL)
     hipStream_t exec;  // stream the batch launches on
     bool own_stream;
@@ -523,6 +530,10 @@ static hipError_t batch_chunk(glbm_batch *b, int k)
     const int32_t *phase = at<int32_t>(b->d_mem, b->o_phase);
     const int64_t *t0 = at<int64_t>(b->d_mem, b->o_t0);
     const KArgs *args = at<KArgs>(b->d_mem, b->o_args);
+    for (auto &r : b->resident) {
+        hipError_t e = r.var->resident(at<int32_t>(b->d_mem, r.list), r.count, args, phase, t0, bstep, k, b->exec);
+        if (e != hipSuccess) return e;
+    }
     for (int l = 0; l < k; ++l)
         for (auto &r : b->sets) {
             hipError_t e = r.var->batch(r.rows, at<BatchTile>(b->d_mem, r.tiles), r.ntiles, b->opt.tile_nodes, args,
@@ -562,9 +573,23 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
         double work;
     };
     const int tile = b->opt.tile_nodes;
+    auto is_resident = [&](const glbm_solver *m) {
+        return b->opt.resident_nodes > 0 && m->geo.nx * m->geo.ny <= (int64_t)b->opt.resident_nodes;
+    };
     std::vector<const Variant *> vars;
     for (int i = 0; i < n; ++i)
         if (std::find(vars.begin(), vars.end(), members[i]->var) == vars.end()) vars.push_back(members[i]->var);
+    // resident member lists per variant
+    std::vector<glbm_batch::ResidentSet> rsets;
+    std::vector<std::vector<int32_t>> rlists;
+    for (const Variant *v : vars) {
+        std::vector<int32_t> ids;
+        for (int i = 0; i < n; ++i)
+            if (members[i]->var == v && is_resident(members[i])) ids.push_back(i);
+        if (ids.empty()) continue;
+        rsets.push_back({v, 0, (int)ids.size()});
+        rlists.push_back(std::move(ids));
+    }
     // tile lists per (variant, row set)
     std::vector<glbm_batch::RowSet> sets;
     std::vector<std::vector<BatchTile>> lists;
@@ -576,7 +601,7 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
             std::vector<Part> parts;
             for (int i = 0; i < n; ++i) {
                 const glbm_solver *m = members[i];
-                if (m->var != v) continue;
+                if (m->var != v || is_resident(m)) continue;
                 const int64_t nx = m->geo.nx, ny = m->geo.ny, ly = m->geo.y.vmax;  // rows with wall emission
                 const int64_t cnt = rows == ROWS_ALL ? nx * ny : rows == ROWS_INTERIOR ? (ny - 2 * ly) * nx : 2 * ly * nx;
                 if (cnt > 0) parts.push_back({i, (int)cnt, (double)cnt * m->geo.q});
@@ -616,8 +641,13 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
         sets[k].tiles = off;
         off = align_up(off + sizeof(BatchTile) * lists[k].size(), 256);
     }
+    for (size_t k = 0; k < rsets.size(); ++k) {
+        rsets[k].list = off;
+        off = align_up(off + sizeof(int32_t) * rlists[k].size(), 256);
+    }
     const size_t need = off;
     b->sets.clear();
+    b->resident.clear();
     release_graph(b);
 
     // the previous upload must have left the pinned copy before it is rewritten
@@ -654,12 +684,15 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
     }
     for (size_t k = 0; k < sets.size(); ++k)
         memcpy(h + sets[k].tiles, lists[k].data(), sizeof(BatchTile) * lists[k].size());
+    for (size_t k = 0; k < rsets.size(); ++k)
+        memcpy(h + rsets[k].list, rlists[k].data(), sizeof(int32_t) * rlists[k].size());
     e = hipMemcpyAsync(b->d_mem, h, need, hipMemcpyHostToDevice, b->exec);
     if (e == hipSuccess) e = hipEventRecord(b->ev_staged, b->exec);
     if (e != hipSuccess) return hip_fail(e, "uploading the batch tables");
     b->sets = std::move(sets);
+    b->resident = std::move(rsets);
 
-    if (b->opt.graph_steps > 0 && !b->sets.empty()) {
+    if (b->opt.graph_steps > 0 && (!b->sets.empty() || !b->resident.empty())) {
         e = hipStreamBeginCapture(b->exec, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             hipError_t ec = batch_chunk(b, b->opt.graph_steps);
@@ -669,6 +702,7 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
         if (e == hipSuccess) e = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             b->sets.clear();
+            b->resident.clear();
             release_graph(b);
             return hip_fail(e, "capturing the batch graph");
         }
@@ -691,7 +725,7 @@ int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_option
 {
     if (!out) return fail(GLBM_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    glbm_batch_options o = {256, GLBM_ORDER_MEMBER, 0};
+    glbm_batch_options o = {256, GLBM_ORDER_MEMBER, 0, 0};
     if (opt) o = *opt;
     if (o.tile_nodes == 0) o.tile_nodes = 256;
     if (o.tile_nodes != 64 && o.tile_nodes != 128 && o.tile_nodes != 256)
@@ -699,6 +733,7 @@ int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_option
     if (o.order < GLBM_ORDER_MEMBER || o.order > GLBM_ORDER_LARGEST_FIRST)
         return fail(GLBM_ERR_INVALID, "unknown tile order");
     if (o.graph_steps < 0) return fail(GLBM_ERR_INVALID, "graph_steps must be >= 0");
+    if (o.resident_nodes < 0) return fail(GLBM_ERR_INVALID, "resident_nodes must be >= 0");
     int rc = check_members(members, n, nullptr);
     if (rc != GLBM_OK) return rc;
 

@@ -443,6 +443,24 @@ struct XAddr {
             return rowb + col[0] + (uint32_t)((V - Axis<LX>::c(a)) * EB);
     }
     __device__ __forceinline__ uint32_t own(uint32_t rowb) const { return rowb + self; }
+    // The same address split into a per-lane part and a uniform part: padded
+    // rows keep one register per row and move the constant column shift to
+    // the scalar offset (which the loads add anyway), so that no address
+    // register per velocity is needed where the compiler does not fold the
+    // shift into the immediate offset.
+    template <int a>
+    __device__ __forceinline__ uint32_t src_lane(uint32_t rowb) const
+    {
+        if constexpr (compact)
+            return rowb + col[a];
+        else
+            return rowb + col[0];
+    }
+    template <int a>
+    static constexpr uint32_t src_uniform()
+    {
+        return compact ? 0u : (uint32_t)((V - Axis<LX>::c(a)) * EB);
+    }
 };
 
 template <int EB>
@@ -738,7 +756,9 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
         unroll<L::QX>([&](auto A) {
             constexpr int a = A, q = b * L::QX + a;
             const uint32_t raw = (uint32_t)__builtin_bit_cast(
-                unsigned short, __builtin_amdgcn_raw_buffer_load_b16(rs, xa.template src<a>(rowb), (uint32_t)q * p.plane_bytes, 0));
+                unsigned short,
+                __builtin_amdgcn_raw_buffer_load_b16(rs, xa.template src_lane<a>(rowb),
+                                                     (uint32_t)q * p.plane_bytes + decltype(xa)::template src_uniform<a>(), 0));
             if constexpr ((q & 1) == 0)
                 pk[q >> 1] = raw;
             else
@@ -846,6 +866,46 @@ __global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchTile *__r
     const int i = row_set_node<LY, ROWS>(t.first + (int)threadIdx.x, p.nx, p.ny);
     if (i < 0) return;
     step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, ST == ST_BF16SR ? step_seed(t0[t.member] + s + 1) : 0u);
+}
+
+// Resident batched steps for small lattices: block b owns member
+// members[b] whole and advances it `steps` steps of a chunk (batch steps
+// *bstep .. *bstep + steps - 1), looping over the member's nodes, with a
+// workgroup barrier between steps (a step's stores, made by this workgroup
+// on this compute unit, are visible to its loads of the next step).  One
+// launch per chunk instead of one per step; every node runs the
+// single-lattice code with the same seeds, so the result is bitwise the
+// lattice stepped alone.  16-bit storage with walls takes its interior rows
+// packed and its wall rows in FP32, as the step launches do.
+template <int LX, int LY, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void resident_step_kernel(const int32_t *__restrict__ members,
+                                                               const KArgs *__restrict__ args,
+                                                               const int32_t *__restrict__ phase,
+                                                               const int64_t *__restrict__ t0,
+                                                               const int64_t *__restrict__ bstep, int32_t steps)
+{
+    constexpr bool split = Elem<ST>::bytes == 2 && BCY == BCY_WALL;
+    const int m = members[blockIdx.x];
+    const int64_t s0 = *bstep;
+    const int ph = phase[m];
+    const int64_t tm = t0[m];
+    for (int l = 0; l < steps; ++l) {
+        const int64_t s = s0 + l;
+        const KArgs &p = args[2 * m + (ph ^ (int)(s & 1))];
+        const uint32_t seed = ST == ST_BF16SR ? step_seed(tm + s + 1) : 0u;
+        if constexpr (split) {
+            constexpr int R = Axis<LY>::vmax;
+            const int interior = (p.ny - 2 * R) * p.nx, walls = 2 * R * p.nx;
+            for (int j = threadIdx.x; j < interior; j += kBlock)
+                step_node<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>(p, row_set_node<LY, ROWS_INTERIOR>(j, p.nx, p.ny), seed);
+            for (int j = threadIdx.x; j < walls; j += kBlock)
+                step_node<LX, LY, ST, BCX, BCY, ROWS_WALLS>(p, row_set_node<LY, ROWS_WALLS>(j, p.nx, p.ny), seed);
+        } else {
+            const int n = p.nx * p.ny;
+            for (int j = threadIdx.x; j < n; j += kBlock) step_node<LX, LY, ST, BCX, BCY, ROWS_ALL>(p, j, seed);
+        }
+        __syncthreads();
+    }
 }
 
 // Moments (and optionally the populations) of the pre-collision state f(t).

@@ -61,6 +61,13 @@ struct Launchers {
                                tiles, args, phase, t0, bstep, launch);
         return hipGetLastError();
     }
+    static hipError_t resident(const int32_t *members, int nmembers, const KArgs *args, const int32_t *phase,
+                               const int64_t *t0, const int64_t *bstep, int steps, hipStream_t s)
+    {
+        hipLaunchKernelGGL((resident_step_kernel<LX, LY, ST, BCX, BCY>), dim3(nmembers), dim3(kBlock), 0, s, members,
+                           args, phase, t0, bstep, steps);
+        return hipGetLastError();
+    }
     static void add()
     {
         Variant *v = variant_slot(LX, LY, ST, BCX, BCY);
@@ -70,6 +77,7 @@ struct Launchers {
         v->stats = &stats;
         v->ends = BCX == BCX_EQ ? &ends : nullptr;
         v->batch = &batch;
+        v->resident = &resident;
         v->split_rows = Elem<ST>::bytes == 2 && BCY == BCY_WALL;
     }
 };

@@ -15,6 +15,10 @@ using LaunchBatch = hipError_t (*)(int rows, const BatchTile *tiles, int ntiles,
                                    const int32_t *phase, const int64_t *t0, const int64_t *bstep, int launch,
                                    hipStream_t);
 
+// Resident batched steps: one block per member, `steps` steps in one launch.
+using LaunchResident = hipError_t (*)(const int32_t *members, int nmembers, const KArgs *args, const int32_t *phase,
+                                      const int64_t *t0, const int64_t *bstep, int steps, hipStream_t);
+
 // Kernels of one (level_x, level_y, storage, bc_x, bc_y) variant.
 struct Variant {
     Launch step = nullptr;
@@ -23,6 +27,7 @@ struct Variant {
     Launch stats = nullptr;
     LaunchEnds ends = nullptr;
     LaunchBatch batch = nullptr;
+    LaunchResident resident = nullptr;
     bool split_rows = false;  // steps run as interior rows + wall rows (16-bit storage with walls)
 };
 

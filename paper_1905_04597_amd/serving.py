@@ -8,10 +8,14 @@ tiles).  Between chunks, finished requests leave (their moments are computed
 on the device and the populations released) and waiting requests join, as
 slots and the device-memory budget allow: continuous batching, not a queue.
 
-Requests are split by size over two lanes, each a batch on its own stream,
-so that the small solves (most requests, little traffic) are not held to the
-pace of the few large ones; the two lanes' kernels share the GPU.  A lane
-re-plans its batch in place (glbm_batch_update) when its members change.
+Requests are split over lanes, each a batch on its own stream: one lane for
+the large solves and several for the small ones (most requests, little
+traffic), so that the small solves are not held to the pace of the large
+ones.  The small solves are spread over their lanes by kernel variant, so the
+lanes' launches proceed side by side on the GPU's hardware queues, and the
+smallest of them run resident (one workgroup, a whole chunk of steps per
+launch).  A lane re-plans its batch in place (glbm_batch_update) when its
+members change.
 
 Admission: the population buffers of all active requests (2 x
 glbm_population_bytes each) stay within the budget (default 200 GB); requests
@@ -26,6 +30,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import time
+import zlib
 from typing import Optional
 
 import numpy as np
@@ -115,26 +120,41 @@ class _Lane:
 
 
 class Server:
-    """Continuous batching over two lanes (small and large requests).
+    """Continuous batching over light lanes (small requests, by kernel
+    variant) and one heavy lane (large requests).
 
     hbm_budget: bytes of population buffers the active requests may hold.
-    light_bytes: a request whose step moves fewer bytes goes to the light lane.
-    chunks: steps per chunk in the (light, heavy) lane.
-    slots: most active requests per lane.
+    light_bytes: a request whose step moves fewer bytes goes to a light lane.
+    light_lanes: number of light lanes.
+    chunks: steps per chunk in a (light, heavy) lane.
+    slots: most active requests per (light, heavy) lane.
+    resident_nodes: light-lane members of at most this many nodes run
+    resident (glbm_batch_options.resident_nodes).
     keep_results: True, or a set of request ids, whose device moments
     {rho, ux, uy, T, pxy} are kept in Request.result."""
 
-    def __init__(self, hbm_budget: float = 200e9, light_bytes: int = 64 << 20, chunks=(50, 20),
-                 slots=(4096, 256), tile_nodes: int = 128, order: str = "interleave",
-                 keep_results: bool = False, clock=time.perf_counter):
+    def __init__(self, hbm_budget: float = 200e9, light_bytes: int = 64 << 20, light_lanes: int = 3,
+                 chunks=(50, 20), slots=(4096, 256), tile_nodes: int = 128, order: str = "interleave",
+                 resident_nodes: int = 2048, keep_results: bool = False, clock=time.perf_counter):
         self.hbm_budget = float(hbm_budget)
         self.light_bytes = int(light_bytes)
         self.keep_results = keep_results
         self.clock = clock
-        opts = dict(tile_nodes=tile_nodes, order=order, graph_steps=0)
-        self.lanes = [_Lane(0, chunks[0], slots[0], opts), _Lane(1, chunks[1], slots[1], opts)]
+        light = dict(tile_nodes=tile_nodes, order=order, graph_steps=0, resident_nodes=resident_nodes)
+        heavy = dict(tile_nodes=tile_nodes, order=order, graph_steps=0, resident_nodes=0)
+        self.nlight = int(light_lanes)
+        self.lanes = [_Lane(i, chunks[0], slots[0], light) for i in range(self.nlight)]
+        self.lanes.append(_Lane(self.nlight, chunks[1], slots[1], heavy))
         self.in_use = 0
         self.peak_in_use = 0
+
+    def _lane_of(self, w) -> int:
+        if step_bytes(w) >= self.light_bytes:
+            return self.nlight
+        # the kernel variant: axes, storage, boundaries, row layout
+        key = "%d/%d%s/%d%s/%s/%s/%s/%d" % (w.dims, w.level_x, "e" if w.even_x else "", w.level_y,
+                                             "e" if w.even_y else "", w.storage, w.bc_x, w.bc_y, w.nx < 64)
+        return zlib.crc32(key.encode()) % self.nlight
 
     def _keep(self, req) -> bool:
         k = self.keep_results
@@ -206,7 +226,7 @@ class Server:
             r.nbytes = 2 * glbm.population_bytes(glbm.config_from_workload(r.workload))
             if r.nbytes > self.hbm_budget:
                 raise glbm.GlbmError("request %d needs %d bytes, above the budget" % (r.rid, r.nbytes))
-            r.lane = 0 if step_bytes(r.workload) < self.light_bytes else 1
+            r.lane = self._lane_of(r.workload)
         pending = collections.deque(sorted(reqs, key=lambda r: r.arrival))
         t0 = self.clock()
         while True:

@@ -78,6 +78,10 @@ def _assert_bitwise(alone, batched, what):
     dict(tile_nodes=256, order="member", graph_steps=0),
     dict(tile_nodes=64, order="interleave", graph_steps=8),
     dict(tile_nodes=128, order="largest_first", graph_steps=5),
+    # small members resident (one workgroup, all steps of a chunk per launch),
+    # the others in tiles
+    dict(tile_nodes=128, order="interleave", graph_steps=0, resident_nodes=1000),
+    dict(tile_nodes=64, order="member", graph_steps=6, resident_nodes=4000),
 ])
 def test_batch_bitwise_equals_alone(opts):
     print("\n[batch] mixed members, options %s" % opts, flush=True)
@@ -111,7 +115,7 @@ def test_batch_update_joins_and_leaves_bitwise():
     for members, k in schedule:
         sol = [batched[i] for i in members]
         if b is None:
-            b = glbm.Batch(sol, tile_nodes=64, order="interleave", graph_steps=3, stream=stream)
+            b = glbm.Batch(sol, tile_nodes=64, order="interleave", graph_steps=3, stream=stream, resident_nodes=500)
         else:
             b.update(sol)
         b.step(k)

@@ -38,7 +38,7 @@ def test_served_results_equal_alone():
     assert srv.in_use == 0
     lat = sorted(r.latency for r in reqs)
     print("[serving] completed %d, lanes %s, latency p50 %.4f s max %.4f s, chunks %s"
-          % (len(reqs), [sum(r.lane == i for r in reqs) for i in (0, 1)], lat[len(lat) // 2], lat[-1],
+          % (len(reqs), [sum(r.lane == i for r in reqs) for i in range(len(srv.lanes))], lat[len(lat) // 2], lat[-1],
              [l.chunks for l in srv.lanes]), flush=True)
     for r in reqs:
         alone = serving.solve_alone(r.workload, r.steps)
