@@ -127,6 +127,8 @@ def run_batched(count: int = 512, steps: int = 2000, storage: str = "f32_shifted
     from paper_1905_04597_amd import batching, glbm
     from paper_1905_04597_amd import workloads as wl
 
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     ws = wl.sweep_workloads(count, steps=steps, storage=storage)
     cfgs = [glbm.config_from_workload(w) for w in ws]
     nodes = sum(w.nodes for w in ws)
@@ -190,6 +192,49 @@ def run_batched(count: int = 512, steps: int = 2000, storage: str = "f32_shifted
     }
 
 
+def run_solves():
+    """Time per solve of the Sod tube (D1Q7, 2000 nodes, Kn = 0.01, 1000 steps)
+    and the Couette channels (G-D2Q49, 4 x 256, Kn 0.01 / 0.1 / 1 / 10, run for
+    the number of steps at which the FP64 reference reached a residual of
+    1e-10: 15300 / 2600 / 5000 / 40500): one launch per step, and the same
+    solve as a one-member resident batch (one workgroup, every step of the
+    solve in one launch).  Both give bitwise the same populations (checked)."""
+    import numpy as np
+    import torch
+    from paper_1905_04597_amd import glbm
+    from paper_1905_04597_amd import workloads as wl
+
+    cases = [("sod_d1q7_2000_kn0.01", wl.sod(2000, 3, 0.01, 1000, storage="f32_shifted"), 1000)]
+    for kn, steps in ((0.01, 15300), (0.1, 2600), (1.0, 5000), (10.0, 40500)):
+        cases.append(("couette_d2q49_4x256_kn%g" % kn, wl.couette(kn, storage="f32_shifted"), steps))
+    out = {}
+    for name, w, steps in cases:
+        times = {}
+        pops = []
+        for mode in ("per_step_launch", "resident"):
+            s = glbm.solver_for(w)
+            if w.init == "sod":
+                rho = wl.sod_density(w.nx, *w.end_rho)
+                s.init_fields(rho, np.zeros_like(rho))
+            else:
+                s.init_fields()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "resident":
+                with glbm.Batch([s], resident_nodes=w.nodes) as b:
+                    b.step(steps)
+            else:
+                s.step(steps)
+            torch.cuda.synchronize()
+            times[mode] = time.perf_counter() - t0
+            pops.append(s.populations())
+            s.close()
+        out[name] = {"steps": steps, "nodes": w.nodes, "velocities": w.nvel,
+                     "ms_per_solve": {k: round(v * 1e3, 2) for k, v in times.items()},
+                     "bitwise_equal": bool(torch.equal(pops[0], pops[1]))}
+    return out
+
+
 def _same_moments(a, b) -> bool:
     import torch
 
@@ -208,6 +253,11 @@ def run_served(duration: float = 12.0, warm: float = 2.0, sample: int = 16, loop
     from paper_1905_04597_amd import serving
     from paper_1905_04597_amd import workloads as wl
 
+    # start from an empty allocator cache: blocks cached by earlier phases of
+    # other sizes would make the server's allocations free and re-allocate
+    # device memory (a device-wide synchronisation) while it runs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     arrivals = wl.served_requests(duration=duration)
     ids = set(int(i) for i in np.linspace(0, len(arrivals) - 1, sample))
     srv = serving.Server(keep_results=ids)
@@ -297,6 +347,7 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if a.served_only:
         print(json.dumps(run_served(a.served_seconds)), flush=True)
+        print(json.dumps(run_solves()), flush=True)
         return 0
     if a.batched_only:
         print(json.dumps(run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)), flush=True)
@@ -322,6 +373,7 @@ def main(argv=None):
                               "frac": round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)})
     batched = None if a.no_batched else run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)
     served = None if a.no_served else run_served(a.served_seconds)
+    solves = None if a.no_served else run_solves()
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.level)
     achieved = main_run["achieved_GBs"]
     line = {
@@ -363,6 +415,8 @@ def main(argv=None):
         line["batched_sweep"] = batched
     if served is not None:
         line["served_mix"] = served
+    if solves is not None:
+        line["single_solves"] = solves
     print(json.dumps(line), flush=True)
     return 0
 

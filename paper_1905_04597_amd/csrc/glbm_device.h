@@ -840,6 +840,19 @@ __global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
     step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, p.seed);
 }
 
+// The packed 16-bit interior rows, asking the register allocator for two
+// waves per SIMD: left to itself the scheduler sinks the packing of loaded
+// pairs to their use (hiding load latency) and ends a few registers above the
+// 256 that two waves allow, halving the bytes in flight of a memory-bound
+// kernel.
+template <int LX, int LY, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel_packed(KArgs p)
+{
+    const int i = row_set_node<LY, ROWS_INTERIOR>(tile_index(p) * kBlock + (int)threadIdx.x, p.nx, p.ny);
+    if (i < 0) return;
+    step_node<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>(p, i, p.seed);
+}
+
 // Batched step: many lattices of one variant in one launch.  Block b takes
 // tile b = (member, first launch index, count) of the table; the member's
 // arguments for this launch's parity are read through the scalar unit, and

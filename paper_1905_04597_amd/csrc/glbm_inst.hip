@@ -18,7 +18,7 @@ struct Launchers {
             constexpr int R = Axis<LY>::vmax;  // rows next to each wall that take emission
             const int interior = (a.ny - 2 * R) * a.nx, walls = 2 * R * a.nx;
             if (interior > 0)
-                hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>),
+                hipLaunchKernelGGL((step_kernel_packed<LX, LY, ST, BCX, BCY>),
                                    dim3((interior + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
             hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>), dim3((walls + kBlock - 1) / kBlock),
                                dim3(kBlock), 0, s, a);

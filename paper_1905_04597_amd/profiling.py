@@ -127,8 +127,8 @@ def main(argv=None):
     w_scale = a.copy_bytes / (write[copy_key] * 1024.0)
     # a time step may be more than one launch (16-bit storage with walls:
     # interior rows and wall rows): sum the step kernels
-    step_keys = [k for k in fetch if "step_kernel" in k[0]]
-    step_stats = [s for s in stats if "step_kernel" in s["name"]]
+    step_keys = [k for k in fetch if "glbm::step_kernel" in k[0]]
+    step_stats = [s for s in stats if "glbm::step_kernel" in s["name"]]
     avg_us = sum(s["avg_us"] for s in step_stats)
     fkib = sum(fetch[k] for k in step_keys)
     wkib = sum(write.get(k, 0.0) for k in step_keys)
