@@ -26,8 +26,11 @@
  *                   v = 2a - (2N+1), a = 0..2N+1; by Eq. temp_2N2 the
  *                   temperature is theta = (4N+3) c^2 / 12 = (4N+3)/3.
  * Velocity ordering and state layout (shared by every array here):
- *   axis x has Qx velocities cx[a], axis y Qy velocities cy[b] (one velocity
- *   0 in one dimension); q = b * Qx + a;  arrays are [q][y][x], x fastest.
+ *   axis x has Qx velocities cx[a], axis y Qy velocities cy[b], axis z Qz
+ *   velocities cz[c] (a single velocity 0 on an absent axis);
+ *   q = (c * Qy + b) * Qx + a;  arrays are [q][z][y][x], x fastest.
+ *   Three dimensions (section 4: the tensor product of three axes) are
+ *   periodic in z.
  *
  * Parity status of each function is stated in its comment; every one of
  * them is pinned by a CPU test (closed forms, worked example of Appendix A,
@@ -125,25 +128,25 @@ double orc_tau_from_kn(double kn, double H, double theta)
 /* ------------------------------------------------------------------ */
 
 typedef struct orc_solver {
-    int dims, Lx, Ly;
-    int kx, ky;       /* axis kinds (ORC_AXIS_*) */
-    int cx[64], cy[64]; /* velocities of the two axes */
-    double u2x, u2y;  /* positivity bounds on u^2 of the two axes (section 3) */
-    int64_t nx, ny;
+    int dims, Lx, Ly, Lz;
+    int kx, ky, kz;   /* axis kinds (ORC_AXIS_*) */
+    int cx[64], cy[64], cz[64]; /* velocities of the three axes */
+    double u2x, u2y, u2z; /* positivity bounds on u^2 of the axes (section 3) */
+    int64_t nx, ny, nz;
     double tau, omega, g;
     int bc_x, bc_y;
     double wall_u[2]; /* x velocity of the bottom (y = -1/2) and top (y = ny - 1/2) wall */
     double end_rho[2];/* densities of the fixed equilibrium ends (x < 0, x >= nx) */
-    int Qx, Qy, Q;
-    double thx, thy;  /* axis temperatures in lattice units */
-    double *Wx, *Wy;  /* rest weights: equilibrium at rho = 1, u = 0 */
+    int Qx, Qy, Qz, Q;
+    double thx, thy, thz; /* axis temperatures in lattice units */
+    double *Wx, *Wy, *Wz; /* rest weights: equilibrium at rho = 1, u = 0 */
     double Jplus_y;   /* half flux sum_{n>0} n W_n of the wall-normal axis */
     double *Ebot, *Etop; /* wall emission per velocity at unit wall density */
     double *f;        /* pre-collision populations f(t) */
     double *fs;       /* post-collision populations f*(t) (scratch) */
     double *fn;       /* next pre-collision state (scratch) */
     double *ux_prev;  /* u_x(t-1) per node, for the steady-state residual */
-    double *rw_bot, *rw_top; /* wall densities (scratch) */
+    double *rw_bot, *rw_top; /* wall densities per (x, z) column (scratch) */
     int64_t t;
 } orc_solver;
 
@@ -153,7 +156,7 @@ static int64_t imod(int64_t a, int64_t m)
     return r < 0 ? r + m : r;
 }
 
-static inline int64_t nodes(const orc_solver *s) { return s->nx * s->ny; }
+static inline int64_t nodes(const orc_solver *s) { return s->nx * s->ny * s->nz; }
 
 /* Velocities, temperature and positivity bound of an axis.  Positivity
  * (section 3): P0 >= 0 of the underlying 2N+1 model, u^2 <= 2 N theta0 with
@@ -173,37 +176,46 @@ static int axis_setup(int kind, int N, int *vel, double *theta, double *u2max)
 }
 
 /* Create a solver.  Returns NULL on an invalid configuration.
- * kind_x, kind_y: ORC_AXIS_ODD or ORC_AXIS_EVEN (ignored for the absent y
- * axis of one dimension).
+ * kind_x, kind_y, kind_z: ORC_AXIS_ODD or ORC_AXIS_EVEN (ignored for absent
+ * axes).  z (three dimensions only) is periodic.
  * tau > 0 is used as given; tau <= 0 derives it from kn (Eq. kn) with the
- * wall distance H = ny (walls half way between nodes) in two dimensions, or
- * the domain length H = nx in one dimension; tau = +inf gives omega = 0. */
-orc_solver *orc_create(int dims, int Lx, int Ly, int kind_x, int kind_y, int64_t nx, int64_t ny, double tau,
-                       double kn, int bc_x, int bc_y, const double *wall_u, const double *end_rho, double g)
+ * wall distance H = ny (walls half way between nodes) in two and three
+ * dimensions, or the domain length H = nx in one dimension; tau = +inf gives
+ * omega = 0. */
+orc_solver *orc_create3(int dims, int Lx, int Ly, int Lz, int kind_x, int kind_y, int kind_z, int64_t nx, int64_t ny,
+                        int64_t nz, double tau, double kn, int bc_x, int bc_y, const double *wall_u,
+                        const double *end_rho, double g)
 {
-    if (dims != 1 && dims != 2) return NULL;
+    if (dims < 1 || dims > 3) return NULL;
     if (dims == 1) { Ly = 0; ny = 1; bc_y = ORC_BC_PERIODIC; kind_y = ORC_AXIS_ODD; }
-    if (Lx < 1 || (dims == 2 && Ly < 1) || nx < 1 || ny < 1) return NULL;
-    if (Lx > 30 || Ly > 30) return NULL;
-    if ((kind_x != ORC_AXIS_ODD && kind_x != ORC_AXIS_EVEN) || (kind_y != ORC_AXIS_ODD && kind_y != ORC_AXIS_EVEN))
+    if (dims < 3) { Lz = 0; nz = 1; kind_z = ORC_AXIS_ODD; }
+    if (Lx < 1 || (dims >= 2 && Ly < 1) || (dims == 3 && Lz < 1) || nx < 1 || ny < 1 || nz < 1) return NULL;
+    if (Lx > 30 || Ly > 30 || Lz > 30) return NULL;
+    if ((kind_x != ORC_AXIS_ODD && kind_x != ORC_AXIS_EVEN) || (kind_y != ORC_AXIS_ODD && kind_y != ORC_AXIS_EVEN) ||
+        (kind_z != ORC_AXIS_ODD && kind_z != ORC_AXIS_EVEN))
         return NULL;
     if (bc_x != ORC_BC_PERIODIC && bc_x != ORC_BC_EQ_ENDS) return NULL;
     if (bc_y != ORC_BC_PERIODIC && bc_y != ORC_BC_WALL) return NULL;
     if (bc_x == ORC_BC_EQ_ENDS && bc_y == ORC_BC_WALL) return NULL;
 
     orc_solver *s = (orc_solver *)calloc(1, sizeof(orc_solver));
-    s->dims = dims; s->Lx = Lx; s->Ly = Ly; s->nx = nx; s->ny = ny;
-    s->kx = kind_x; s->ky = kind_y;
+    s->dims = dims; s->Lx = Lx; s->Ly = Ly; s->Lz = Lz; s->nx = nx; s->ny = ny; s->nz = nz;
+    s->kx = kind_x; s->ky = kind_y; s->kz = kind_z;
     s->bc_x = bc_x; s->bc_y = bc_y; s->g = g;
     s->wall_u[0] = wall_u ? wall_u[0] : 0.0; s->wall_u[1] = wall_u ? wall_u[1] : 0.0;
     s->end_rho[0] = end_rho ? end_rho[0] : 1.0; s->end_rho[1] = end_rho ? end_rho[1] : 1.0;
     s->Qx = axis_setup(kind_x, Lx, s->cx, &s->thx, &s->u2x);
-    if (dims == 2) {
+    if (dims >= 2) {
         s->Qy = axis_setup(kind_y, Ly, s->cy, &s->thy, &s->u2y);
     } else {
         s->Qy = 1; s->cy[0] = 0; s->thy = 0.0; s->u2y = 0.0;
     }
-    s->Q = s->Qx * s->Qy;
+    if (dims == 3) {
+        s->Qz = axis_setup(kind_z, Lz, s->cz, &s->thz, &s->u2z);
+    } else {
+        s->Qz = 1; s->cz[0] = 0; s->thz = 0.0; s->u2z = 0.0;
+    }
+    s->Q = s->Qx * s->Qy * s->Qz;
     /* no population may cross both walls in one step */
     if (s->Q > 4096 || (bc_y == ORC_BC_WALL && ny < 2 * s->cy[s->Qy - 1])) {
         free(s);
@@ -212,8 +224,8 @@ orc_solver *orc_create(int dims, int Lx, int Ly, int kind_x, int kind_y, int64_t
     if (tau > 0.0) {
         s->tau = tau;
     } else {
-        const double H = dims == 2 ? (double)ny : (double)nx;
-        const double th = dims == 2 ? s->thy : s->thx;
+        const double H = dims >= 2 ? (double)ny : (double)nx;
+        const double th = dims >= 2 ? s->thy : s->thx;
         s->tau = orc_tau_from_kn(kn, H, th);
     }
     /* collision frequency Delta t / (tau + Delta t / 2), section 2 */
@@ -221,8 +233,10 @@ orc_solver *orc_create(int dims, int Lx, int Ly, int kind_x, int kind_y, int64_t
 
     s->Wx = (double *)calloc(s->Qx, sizeof(double));
     s->Wy = (double *)calloc(s->Qy, sizeof(double));
+    s->Wz = (double *)calloc(s->Qz, sizeof(double));
     orc_axis_equilibrium(kind_x, Lx, 0.0, s->Wx);
-    if (dims == 2) orc_axis_equilibrium(kind_y, Ly, 0.0, s->Wy); else s->Wy[0] = 1.0;
+    if (dims >= 2) orc_axis_equilibrium(kind_y, Ly, 0.0, s->Wy); else s->Wy[0] = 1.0;
+    if (dims == 3) orc_axis_equilibrium(kind_z, Lz, 0.0, s->Wz); else s->Wz[0] = 1.0;
     s->Jplus_y = 0.0;
     for (int b = 0; b < s->Qy; ++b)
         if (s->cy[b] > 0) s->Jplus_y += s->cy[b] * s->Wy[b];
@@ -233,12 +247,13 @@ orc_solver *orc_create(int dims, int Lx, int Ly, int kind_x, int kind_y, int64_t
     double *Ft = (double *)calloc(s->Qx, sizeof(double));
     orc_axis_equilibrium(kind_x, Lx, s->wall_u[0], Fb);
     orc_axis_equilibrium(kind_x, Lx, s->wall_u[1], Ft);
-    for (int b = 0; b < s->Qy; ++b)
-        for (int a = 0; a < s->Qx; ++a) {
-            const int q = b * s->Qx + a;
-            s->Ebot[q] = Fb[a] * s->Wy[b];
-            s->Etop[q] = Ft[a] * s->Wy[b];
-        }
+    for (int c = 0; c < s->Qz; ++c)
+        for (int b = 0; b < s->Qy; ++b)
+            for (int a = 0; a < s->Qx; ++a) {
+                const int q = (c * s->Qy + b) * s->Qx + a;
+                s->Ebot[q] = Fb[a] * s->Wy[b] * s->Wz[c];
+                s->Etop[q] = Ft[a] * s->Wy[b] * s->Wz[c];
+            }
     free(Fb); free(Ft);
 
     const int64_t n = nodes(s);
@@ -246,16 +261,25 @@ orc_solver *orc_create(int dims, int Lx, int Ly, int kind_x, int kind_y, int64_t
     s->fs = (double *)calloc((size_t)(s->Q * n), sizeof(double));
     s->fn = (double *)calloc((size_t)(s->Q * n), sizeof(double));
     s->ux_prev = (double *)calloc((size_t)n, sizeof(double));
-    s->rw_bot = (double *)calloc((size_t)nx, sizeof(double));
-    s->rw_top = (double *)calloc((size_t)nx, sizeof(double));
+    s->rw_bot = (double *)calloc((size_t)(nx * nz), sizeof(double));
+    s->rw_top = (double *)calloc((size_t)(nx * nz), sizeof(double));
     s->t = 0;
     return s;
+}
+
+/* One or two dimensions (orc_create3 with no z axis). */
+orc_solver *orc_create(int dims, int Lx, int Ly, int kind_x, int kind_y, int64_t nx, int64_t ny, double tau,
+                       double kn, int bc_x, int bc_y, const double *wall_u, const double *end_rho, double g)
+{
+    if (dims != 1 && dims != 2) return NULL;
+    return orc_create3(dims, Lx, Ly, 0, kind_x, kind_y, ORC_AXIS_ODD, nx, ny, 1, tau, kn, bc_x, bc_y, wall_u,
+                       end_rho, g);
 }
 
 void orc_destroy(orc_solver *s)
 {
     if (!s) return;
-    free(s->Wx); free(s->Wy); free(s->Ebot); free(s->Etop);
+    free(s->Wx); free(s->Wy); free(s->Wz); free(s->Ebot); free(s->Etop);
     free(s->f); free(s->fs); free(s->fn); free(s->ux_prev);
     free(s->rw_bot); free(s->rw_top);
     free(s);
@@ -273,6 +297,12 @@ int orc_axis_velocities(const orc_solver *s, int *cx, int *cy)
     return s->Qx;
 }
 
+int orc_axis_velocities_z(const orc_solver *s, int *cz)
+{
+    memcpy(cz, s->cz, sizeof(int) * s->Qz);
+    return s->Qz;
+}
+
 /* Rest weights of the two axes and the wall-normal half flux. */
 void orc_tables(const orc_solver *s, double *Wx, double *Wy, double *jplus)
 {
@@ -281,29 +311,37 @@ void orc_tables(const orc_solver *s, double *Wx, double *Wy, double *jplus)
     *jplus = s->Jplus_y;
 }
 
-/* Tensor-product equilibrium (section 4): f^eq_ab = rho F_a(u_x) F_b(u_y). */
-static void equilibrium_node(const orc_solver *s, double rho, double ux, double uy, double *feq)
+/* Tensor-product equilibrium (section 4):
+ * f^eq_abc = rho F_a(u_x) F_b(u_y) F_c(u_z). */
+static void equilibrium_node(const orc_solver *s, double rho, double ux, double uy, double uz, double *feq)
 {
-    double Fx[64], Fy[64];
+    double Fx[64], Fy[64], Fz[64];
     orc_axis_equilibrium(s->kx, s->Lx, ux, Fx);
-    if (s->dims == 2) orc_axis_equilibrium(s->ky, s->Ly, uy, Fy); else Fy[0] = 1.0;
-    for (int b = 0; b < s->Qy; ++b)
-        for (int a = 0; a < s->Qx; ++a) feq[b * s->Qx + a] = rho * Fx[a] * Fy[b];
+    if (s->dims >= 2) orc_axis_equilibrium(s->ky, s->Ly, uy, Fy); else Fy[0] = 1.0;
+    if (s->dims == 3) orc_axis_equilibrium(s->kz, s->Lz, uz, Fz); else Fz[0] = 1.0;
+    for (int c = 0; c < s->Qz; ++c)
+        for (int b = 0; b < s->Qy; ++b)
+            for (int a = 0; a < s->Qx; ++a) feq[(c * s->Qy + b) * s->Qx + a] = rho * Fx[a] * Fy[b] * Fz[c];
 }
 
-/* f(0) = f^eq(rho, u) per node; uy may be NULL (zero). */
-void orc_init_fields(orc_solver *s, const double *rho, const double *ux, const double *uy)
+/* f(0) = f^eq(rho, u) per node; uy and uz may be NULL (zero). */
+void orc_init_fields3(orc_solver *s, const double *rho, const double *ux, const double *uy, const double *uz)
 {
     const int64_t n = nodes(s);
     double feq[4096];
     for (int64_t k = 0; k < n; ++k) {
-        equilibrium_node(s, rho ? rho[k] : 1.0, ux ? ux[k] : 0.0, uy ? uy[k] : 0.0, feq);
+        equilibrium_node(s, rho ? rho[k] : 1.0, ux ? ux[k] : 0.0, uy ? uy[k] : 0.0, uz ? uz[k] : 0.0, feq);
         for (int q = 0; q < s->Q; ++q) s->f[q * n + k] = feq[q];
     }
     s->t = 0;
 }
 
-/* f(0) given directly, [q][y][x]. */
+void orc_init_fields(orc_solver *s, const double *rho, const double *ux, const double *uy)
+{
+    orc_init_fields3(s, rho, ux, uy, NULL);
+}
+
+/* f(0) given directly, [q][z][y][x]. */
 void orc_init_populations(orc_solver *s, const double *f0)
 {
     memcpy(s->f, f0, sizeof(double) * (size_t)(s->Q * nodes(s)));
@@ -316,79 +354,88 @@ void orc_get_populations(const orc_solver *s, double *out)
 }
 
 /* Density and velocity of node k of a state (section 2 moment definitions). */
-static void node_rho_u(const orc_solver *s, const double *f, int64_t k, double *rho, double *ux, double *uy)
+static void node_rho_u(const orc_solver *s, const double *f, int64_t k, double *rho, double *ux, double *uy,
+                       double *uz)
 {
     const int64_t n = nodes(s);
-    double r = 0, jx = 0, jy = 0;
-    for (int b = 0; b < s->Qy; ++b)
-        for (int a = 0; a < s->Qx; ++a) {
-            const double v = f[(b * s->Qx + a) * n + k];
-            r += v;
-            jx += v * s->cx[a];
-            jy += v * s->cy[b];
-        }
-    *rho = r; *ux = jx / r; *uy = jy / r;
+    double r = 0, jx = 0, jy = 0, jz = 0;
+    for (int c = 0; c < s->Qz; ++c)
+        for (int b = 0; b < s->Qy; ++b)
+            for (int a = 0; a < s->Qx; ++a) {
+                const double v = f[((c * s->Qy + b) * s->Qx + a) * n + k];
+                r += v;
+                jx += v * s->cx[a];
+                jy += v * s->cy[b];
+                jz += v * s->cz[c];
+            }
+    *rho = r; *ux = jx / r; *uy = jy / r; *uz = jz / r;
 }
 
 /* Collision of every node (Eq. maineq01 right-hand side plus the linear
  * force of section 5.4): f* = f + omega (f^eq - f) + F,
- * F_ab = W_a W_b c_a g / theta_x, which adds momentum g and no mass. */
+ * F_abc = W_a W_b W_c c_a g / theta_x, which adds momentum g and no mass. */
 static void collide_all(const orc_solver *s, const double *f, double *fs, double *ux_out)
 {
     const int64_t n = nodes(s);
     double feq[4096];
     for (int64_t k = 0; k < n; ++k) {
-        double rho, ux, uy;
-        node_rho_u(s, f, k, &rho, &ux, &uy);
+        double rho, ux, uy, uz;
+        node_rho_u(s, f, k, &rho, &ux, &uy, &uz);
         if (ux_out) ux_out[k] = ux;
-        equilibrium_node(s, rho, ux, uy, feq);
-        for (int b = 0; b < s->Qy; ++b)
-            for (int a = 0; a < s->Qx; ++a) {
-                const int q = b * s->Qx + a;
-                const double force = s->Wx[a] * s->Wy[b] * s->cx[a] * s->g / s->thx;
-                const double v = f[q * n + k];
-                fs[q * n + k] = v + s->omega * (feq[q] - v) + force;
-            }
+        equilibrium_node(s, rho, ux, uy, uz, feq);
+        for (int c = 0; c < s->Qz; ++c)
+            for (int b = 0; b < s->Qy; ++b)
+                for (int a = 0; a < s->Qx; ++a) {
+                    const int q = (c * s->Qy + b) * s->Qx + a;
+                    const double force = s->Wx[a] * s->Wy[b] * s->Wz[c] * s->cx[a] * s->g / s->thx;
+                    const double v = f[q * n + k];
+                    fs[q * n + k] = v + s->omega * (feq[q] - v) + force;
+                }
     }
 }
 
 /* Diffuse-reflection wall densities.  The paper cites the kinetic wall
  * condition without writing it out (sections 5.3, 5.4); the reading used
  * here: every post-collision population whose streaming would cross a wall
- * is absorbed and attributed to the column it would have reached; the wall
- * re-emits that mass into the same column as the equilibrium at the wall
- * velocity, rho_w(x) E_i, over the populations that point into the fluid,
- * so rho_w(x) = absorbed(x) / J+ with J+ = sum_{c>0} c W_c. */
+ * is absorbed and attributed to the column (x, z) it would have reached; the
+ * wall re-emits that mass into the same column as the equilibrium at the
+ * wall velocity, rho_w E_i, over the populations that point into the fluid,
+ * so rho_w = absorbed / J+ with J+ = sum_{c>0} c W_c.  Arrays per column
+ * are [z][x]. */
 static void wall_densities(const orc_solver *s, const double *fs, double *rw_bot, double *rw_top,
                            double *mom_bot, double *mom_top)
 {
-    const int64_t n = nodes(s), nx = s->nx, ny = s->ny;
-    for (int64_t x = 0; x < nx; ++x) {
-        double ab = 0, at = 0, pb = 0, pt = 0;
-        for (int b = 0; b < s->Qy; ++b) {
-            const int cb = s->cy[b];
-            for (int a = 0; a < s->Qx; ++a) {
-                const int ca = s->cx[a];
-                const int q = b * s->Qx + a;
-                const int64_t xs = imod(x - ca, nx);
-                if (cb < 0) {
-                    for (int64_t y = 0; y < -cb; ++y) {
-                        const double v = fs[q * n + y * nx + xs];
-                        ab += v; pb += v * ca;
-                    }
-                } else if (cb > 0) {
-                    for (int64_t y = ny - cb; y < ny; ++y) {
-                        const double v = fs[q * n + y * nx + xs];
-                        at += v; pt += v * ca;
+    const int64_t n = nodes(s), nx = s->nx, ny = s->ny, nz = s->nz;
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t x = 0; x < nx; ++x) {
+            double ab = 0, at = 0, pb = 0, pt = 0;
+            for (int c = 0; c < s->Qz; ++c) {
+                const int64_t zs = imod(z - s->cz[c], nz);
+                for (int b = 0; b < s->Qy; ++b) {
+                    const int cb = s->cy[b];
+                    for (int a = 0; a < s->Qx; ++a) {
+                        const int ca = s->cx[a];
+                        const int q = (c * s->Qy + b) * s->Qx + a;
+                        const int64_t xs = imod(x - ca, nx);
+                        if (cb < 0) {
+                            for (int64_t y = 0; y < -cb; ++y) {
+                                const double v = fs[q * n + (zs * ny + y) * nx + xs];
+                                ab += v; pb += v * ca;
+                            }
+                        } else if (cb > 0) {
+                            for (int64_t y = ny - cb; y < ny; ++y) {
+                                const double v = fs[q * n + (zs * ny + y) * nx + xs];
+                                at += v; pt += v * ca;
+                            }
+                        }
                     }
                 }
             }
+            rw_bot[z * nx + x] = ab / s->Jplus_y;
+            rw_top[z * nx + x] = at / s->Jplus_y;
+            if (mom_bot) mom_bot[z * nx + x] = pb;
+            if (mom_top) mom_top[z * nx + x] = pt;
         }
-        rw_bot[x] = ab / s->Jplus_y;
-        rw_top[x] = at / s->Jplus_y;
-        if (mom_bot) mom_bot[x] = pb;
-        if (mom_top) mom_top[x] = pt;
-    }
 }
 
 /* Linear streaming (left-hand side of Eq. maineq01), written in pull form:
@@ -396,33 +443,39 @@ static void wall_densities(const orc_solver *s, const double *fs, double *rw_bot
  * equilibrium ends where x - c_i lies outside the domain. */
 static void stream_all(const orc_solver *s, const double *fs, double *fn)
 {
-    const int64_t n = nodes(s), nx = s->nx, ny = s->ny;
-    for (int b = 0; b < s->Qy; ++b) {
-        const int cb = s->cy[b];
-        for (int a = 0; a < s->Qx; ++a) {
-            const int ca = s->cx[a];
-            const int q = b * s->Qx + a;
-            for (int64_t y = 0; y < ny; ++y)
-                for (int64_t x = 0; x < nx; ++x) {
-                    int64_t ys = y - cb, xs = x - ca;
-                    double v;
-                    if (s->bc_y == ORC_BC_WALL && ys < 0) {
-                        v = s->rw_bot[x] * s->Ebot[q];
-                    } else if (s->bc_y == ORC_BC_WALL && ys >= ny) {
-                        v = s->rw_top[x] * s->Etop[q];
-                    } else {
-                        ys = imod(ys, ny);
-                        if (s->bc_x == ORC_BC_EQ_ENDS && xs < 0) {
-                            v = s->end_rho[0] * s->Wx[a] * s->Wy[b];
-                        } else if (s->bc_x == ORC_BC_EQ_ENDS && xs >= nx) {
-                            v = s->end_rho[1] * s->Wx[a] * s->Wy[b];
-                        } else {
-                            xs = imod(xs, nx);
-                            v = fs[q * n + ys * nx + xs];
+    const int64_t n = nodes(s), nx = s->nx, ny = s->ny, nz = s->nz;
+    for (int c = 0; c < s->Qz; ++c) {
+        const int cc = s->cz[c];
+        for (int b = 0; b < s->Qy; ++b) {
+            const int cb = s->cy[b];
+            for (int a = 0; a < s->Qx; ++a) {
+                const int ca = s->cx[a];
+                const int q = (c * s->Qy + b) * s->Qx + a;
+                for (int64_t z = 0; z < nz; ++z) {
+                    const int64_t zs = imod(z - cc, nz);
+                    for (int64_t y = 0; y < ny; ++y)
+                        for (int64_t x = 0; x < nx; ++x) {
+                            int64_t ys = y - cb, xs = x - ca;
+                            double v;
+                            if (s->bc_y == ORC_BC_WALL && ys < 0) {
+                                v = s->rw_bot[z * nx + x] * s->Ebot[q];
+                            } else if (s->bc_y == ORC_BC_WALL && ys >= ny) {
+                                v = s->rw_top[z * nx + x] * s->Etop[q];
+                            } else {
+                                ys = imod(ys, ny);
+                                if (s->bc_x == ORC_BC_EQ_ENDS && xs < 0) {
+                                    v = s->end_rho[0] * s->Wx[a] * s->Wy[b] * s->Wz[c];
+                                } else if (s->bc_x == ORC_BC_EQ_ENDS && xs >= nx) {
+                                    v = s->end_rho[1] * s->Wx[a] * s->Wy[b] * s->Wz[c];
+                                } else {
+                                    xs = imod(xs, nx);
+                                    v = fs[q * n + (zs * ny + ys) * nx + xs];
+                                }
+                            }
+                            fn[q * n + (z * ny + y) * nx + x] = v;
                         }
-                    }
-                    fn[q * n + y * nx + x] = v;
                 }
+            }
         }
     }
 }
@@ -442,25 +495,32 @@ void orc_step(orc_solver *s, int64_t nsteps)
 /* Moments of the pre-collision state f(t): rho, u, the temperature per
  * degree of freedom T = (sum f |c|^2 / rho - |u|^2) / D and the shear
  * moment Pxy = sum f c_x c_y - rho u_x u_y.  Any output may be NULL. */
-void orc_moments(const orc_solver *s, double *rho, double *ux, double *uy, double *T, double *pxy)
+void orc_moments3(const orc_solver *s, double *rho, double *ux, double *uy, double *uz, double *T, double *pxy)
 {
     const int64_t n = nodes(s);
     for (int64_t k = 0; k < n; ++k) {
-        double r = 0, jx = 0, jy = 0, exx = 0, eyy = 0, exy = 0;
-        for (int b = 0; b < s->Qy; ++b)
-            for (int a = 0; a < s->Qx; ++a) {
-                const double v = s->f[(b * s->Qx + a) * n + k];
-                const double ca = s->cx[a], cb = s->cy[b];
-                r += v; jx += v * ca; jy += v * cb;
-                exx += v * ca * ca; eyy += v * cb * cb; exy += v * ca * cb;
-            }
-        const double vx = jx / r, vy = jy / r;
+        double r = 0, jx = 0, jy = 0, jz = 0, exx = 0, eyy = 0, ezz = 0, exy = 0;
+        for (int c = 0; c < s->Qz; ++c)
+            for (int b = 0; b < s->Qy; ++b)
+                for (int a = 0; a < s->Qx; ++a) {
+                    const double v = s->f[((c * s->Qy + b) * s->Qx + a) * n + k];
+                    const double ca = s->cx[a], cb = s->cy[b], cc = s->cz[c];
+                    r += v; jx += v * ca; jy += v * cb; jz += v * cc;
+                    exx += v * ca * ca; eyy += v * cb * cb; ezz += v * cc * cc; exy += v * ca * cb;
+                }
+        const double vx = jx / r, vy = jy / r, vz = jz / r;
         if (rho) rho[k] = r;
         if (ux) ux[k] = vx;
         if (uy) uy[k] = vy;
-        if (T) T[k] = ((exx + eyy) / r - vx * vx - vy * vy) / s->dims;
+        if (uz) uz[k] = vz;
+        if (T) T[k] = ((exx + eyy + ezz) / r - vx * vx - vy * vy - vz * vz) / s->dims;
         if (pxy) pxy[k] = exy - r * vx * vy;
     }
+}
+
+void orc_moments(const orc_solver *s, double *rho, double *ux, double *uy, double *T, double *pxy)
+{
+    orc_moments3(s, rho, ux, uy, NULL, T, pxy);
 }
 
 /* Kahan-compensated running sum. */
@@ -485,44 +545,47 @@ static void kadd(ksum *k, double v)
  *  out[7] x momentum given to the bottom wall in the next streaming
  *  out[8] x momentum given to the top wall
  *  out[9] number of nodes outside the positivity domain of section 3 on
- *         either axis (see axis_setup) */
+ *         any axis (see axis_setup)
+ *  out[10] momentum z  sum f(t) c_z */
 void orc_stats(orc_solver *s, double *out)
 {
-    const int64_t n = nodes(s), nx = s->nx;
-    ksum m = {0, 0}, px = {0, 0}, py = {0, 0}, e = {0, 0}, d2 = {0, 0}, u2 = {0, 0};
+    const int64_t n = nodes(s), ncol = s->nx * s->nz;
+    ksum m = {0, 0}, px = {0, 0}, py = {0, 0}, pz = {0, 0}, e = {0, 0}, d2 = {0, 0}, u2 = {0, 0};
     double *ux = (double *)malloc(sizeof(double) * (size_t)n);
     collide_all(s, s->f, s->fs, ux);
     double npos = 0;
     for (int64_t k = 0; k < n; ++k) {
-        double r = 0, jx = 0, jy = 0, en = 0;
-        for (int b = 0; b < s->Qy; ++b)
-            for (int a = 0; a < s->Qx; ++a) {
-                const int q = b * s->Qx + a;
-                const double ca = s->cx[a], cb = s->cy[b];
-                const double v = s->f[q * n + k];
-                r += v; jx += v * ca; jy += v * cb;
-                en += s->fs[q * n + k] * (ca * ca + cb * cb);
-            }
-        kadd(&m, r); kadd(&px, jx); kadd(&py, jy); kadd(&e, en);
+        double r = 0, jx = 0, jy = 0, jz = 0, en = 0;
+        for (int c = 0; c < s->Qz; ++c)
+            for (int b = 0; b < s->Qy; ++b)
+                for (int a = 0; a < s->Qx; ++a) {
+                    const int q = (c * s->Qy + b) * s->Qx + a;
+                    const double ca = s->cx[a], cb = s->cy[b], cc = s->cz[c];
+                    const double v = s->f[q * n + k];
+                    r += v; jx += v * ca; jy += v * cb; jz += v * cc;
+                    en += s->fs[q * n + k] * (ca * ca + cb * cb + cc * cc);
+                }
+        kadd(&m, r); kadd(&px, jx); kadd(&py, jy); kadd(&pz, jz); kadd(&e, en);
         kadd(&u2, ux[k] * ux[k]);
         kadd(&d2, (ux[k] - s->ux_prev[k]) * (ux[k] - s->ux_prev[k]));
-        const double vy = jy / r;
-        if (ux[k] * ux[k] > s->u2x || (s->dims == 2 && vy * vy > s->u2y)) npos += 1;
+        const double vy = jy / r, vz = jz / r;
+        if (ux[k] * ux[k] > s->u2x || (s->dims >= 2 && vy * vy > s->u2y) || (s->dims == 3 && vz * vz > s->u2z))
+            npos += 1;
     }
     out[0] = m.s; out[1] = px.s; out[2] = py.s; out[3] = e.s;
     out[4] = s->t > 0 ? sqrt(d2.s) / sqrt(u2.s) : NAN;
     out[5] = out[6] = out[7] = out[8] = 0.0;
     if (s->bc_y == ORC_BC_WALL) {
-        double *pb = (double *)malloc(sizeof(double) * (size_t)nx);
-        double *pt = (double *)malloc(sizeof(double) * (size_t)nx);
-        double *rb = (double *)malloc(sizeof(double) * (size_t)nx);
-        double *rt = (double *)malloc(sizeof(double) * (size_t)nx);
+        double *pb = (double *)malloc(sizeof(double) * (size_t)ncol);
+        double *pt = (double *)malloc(sizeof(double) * (size_t)ncol);
+        double *rb = (double *)malloc(sizeof(double) * (size_t)ncol);
+        double *rt = (double *)malloc(sizeof(double) * (size_t)ncol);
         wall_densities(s, s->fs, rb, rt, pb, pt);
         ksum ab = {0, 0}, at = {0, 0}, mb = {0, 0}, mt = {0, 0};
-        for (int64_t x = 0; x < nx; ++x) {
+        for (int64_t x = 0; x < ncol; ++x) {
             const double Ab = rb[x] * s->Jplus_y, At = rt[x] * s->Jplus_y;
             kadd(&ab, Ab); kadd(&at, At);
-            /* emitted x momentum per column is A(x) U_w: the first moment of
+            /* emitted x momentum per column is A U_w: the first moment of
              * the unit-density equilibrium at the wall velocity is U_w */
             kadd(&mb, pb[x] - Ab * s->wall_u[0]);
             kadd(&mt, pt[x] - At * s->wall_u[1]);
@@ -531,5 +594,6 @@ void orc_stats(orc_solver *s, double *out)
         free(pb); free(pt); free(rb); free(rt);
     }
     out[9] = npos;
+    out[10] = pz.s;
     free(ux);
 }

@@ -62,6 +62,16 @@ def _load():
             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double,
         ]
         lib.orc_create.restype = ctypes.c_void_p
+        lib.orc_create3.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double,
+        ]
+        lib.orc_create3.restype = ctypes.c_void_p
+        lib.orc_axis_velocities_z.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_axis_velocities_z.restype = ctypes.c_int
+        lib.orc_init_fields3.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
+        lib.orc_moments3.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.orc_destroy.argtypes = [ctypes.c_void_p]
         lib.orc_tau.argtypes = [ctypes.c_void_p]
         lib.orc_tau.restype = ctypes.c_double
@@ -150,33 +160,40 @@ class OracleSolver:
     STAT_NAMES = (
         "mass", "momentum_x", "momentum_y", "energy_post", "residual",
         "wall_mass_bottom", "wall_mass_top", "wall_momentum_bottom", "wall_momentum_top",
-        "nonpositive_nodes",
+        "nonpositive_nodes", "momentum_z",
     )
 
     def __init__(self, dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0,
                  bc_x=BC_PERIODIC, bc_y=BC_PERIODIC, wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0,
-                 even_x=False, even_y=False):
+                 even_x=False, even_y=False, level_z=0, nz=1, even_z=False):
+        """dims 1, 2 or 3; a third axis (level_z, nz, even_z) is periodic."""
         self._lib = _load()
         wu = np.asarray(wall_u, dtype=np.float64)
         er = np.asarray(end_rho, dtype=np.float64)
-        h = self._lib.orc_create(int(dims), int(level_x), int(level_y), AXIS_EVEN if even_x else AXIS_ODD,
-                                 AXIS_EVEN if even_y else AXIS_ODD, int(nx), int(ny),
-                                 float(tau), float(kn), int(bc_x), int(bc_y), _ptr(wu), _ptr(er), float(g))
+        h = self._lib.orc_create3(int(dims), int(level_x), int(level_y), int(level_z),
+                                  AXIS_EVEN if even_x else AXIS_ODD, AXIS_EVEN if even_y else AXIS_ODD,
+                                  AXIS_EVEN if even_z else AXIS_ODD, int(nx), int(ny), int(nz),
+                                  float(tau), float(kn), int(bc_x), int(bc_y), _ptr(wu), _ptr(er), float(g))
         if not h:
             raise ValueError("oracle rejected the configuration")
         self._h = h
         self.dims = int(dims)
         self.level_x = int(level_x)
         self.level_y = int(level_y) if dims == 2 else 0
+        self.level_z = int(level_z) if dims == 3 else 0
         self.nx = int(nx)
-        self.ny = int(ny) if dims == 2 else 1
+        self.ny = int(ny) if dims >= 2 else 1
+        self.nz = int(nz) if dims == 3 else 1
         self.Q = self._lib.orc_nvel(h)
         cx = (ctypes.c_int * 64)()
         cy = (ctypes.c_int * 64)()
+        cz = (ctypes.c_int * 64)()
         self.Qx = self._lib.orc_axis_velocities(h, cx, cy)
-        self.Qy = self.Q // self.Qx
+        self.Qz = self._lib.orc_axis_velocities_z(h, cz)
+        self.Qy = self.Q // (self.Qx * self.Qz)
         self.cx = np.array(cx[:self.Qx])
         self.cy = np.array(cy[:self.Qy])
+        self.cz = np.array(cz[:self.Qz])
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -198,7 +215,10 @@ class OracleSolver:
 
     @property
     def nodes(self):
-        return self.nx * self.ny
+        return self.nx * self.ny * self.nz
+
+    def _shape(self):
+        return (self.nz, self.ny, self.nx) if self.dims == 3 else (self.ny, self.nx)
 
     def velocities(self):
         return self.cx.copy(), self.cy.copy()
@@ -210,10 +230,10 @@ class OracleSolver:
         self._lib.orc_tables(self._h, _ptr(Wx), _ptr(Wy), _ptr(jp))
         return Wx, Wy, float(jp[0])
 
-    def init_fields(self, rho=None, ux=None, uy=None):
+    def init_fields(self, rho=None, ux=None, uy=None, uz=None):
         n = self.nodes
-        r, a, b = _f64(rho, n), _f64(ux, n), _f64(uy, n)
-        self._lib.orc_init_fields(self._h, _ptr(r), _ptr(a), _ptr(b))
+        r, a, b, c = _f64(rho, n), _f64(ux, n), _f64(uy, n), _f64(uz, n)
+        self._lib.orc_init_fields3(self._h, _ptr(r), _ptr(a), _ptr(b), _ptr(c))
 
     def init_populations(self, f0):
         f0 = _f64(f0, self.Q * self.nodes)
@@ -222,16 +242,20 @@ class OracleSolver:
     def populations(self) -> np.ndarray:
         out = np.zeros(self.Q * self.nodes)
         self._lib.orc_get_populations(self._h, _ptr(out))
-        return out.reshape(self.Q, self.ny, self.nx)
+        return out.reshape((self.Q,) + self._shape())
 
     def step(self, n: int = 1):
         self._lib.orc_step(self._h, int(n))
 
     def moments(self) -> dict:
+        """rho, ux, uy, T, pxy (and uz in three dimensions), shaped like the lattice."""
         n = self.nodes
-        out = {k: np.zeros(n) for k in ("rho", "ux", "uy", "T", "pxy")}
-        self._lib.orc_moments(self._h, *[_ptr(out[k]) for k in ("rho", "ux", "uy", "T", "pxy")])
-        return {k: v.reshape(self.ny, self.nx) for k, v in out.items()}
+        keys = ("rho", "ux", "uy", "uz", "T", "pxy")
+        out = {k: np.zeros(n) for k in keys}
+        self._lib.orc_moments3(self._h, *[_ptr(out[k]) for k in keys])
+        if self.dims < 3:
+            del out["uz"]
+        return {k: v.reshape(self._shape()) for k, v in out.items()}
 
     def stats(self) -> dict:
         out = np.zeros(len(self.STAT_NAMES))

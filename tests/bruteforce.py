@@ -142,3 +142,80 @@ def from_dict(d, Lx, Ly, nx, ny, even_x=False, even_y=False):
     for (x, y, cx, cy), v in d.items():
         arr[iy[cy] * len(vx) + ix[cx], y, x] = v
     return arr
+
+
+def run3(Lx, Ly, Lz, nx, ny, nz, omega, g, bc_y, wall_u, f0, steps, even=(False, False, False)):
+    """Three dimensions (periodic x and z, y periodic or diffuse walls):
+    ``f0`` is a dict {(x, y, z, cx, cy, cz): value}."""
+    ex, ey, ez = even
+    vel = [(cx, cy, cz) for cz in axis_velocities(Lz, ez) for cy in axis_velocities(Ly, ey)
+           for cx in axis_velocities(Lx, ex)]
+    Wx, Wy, Wz = axis_law(Lx, ex, 0.0), axis_law(Ly, ey, 0.0), axis_law(Lz, ez, 0.0)
+    thx = sum(Wx[c] * c * c for c in Wx)
+    jplus = sum(cy * Wy[cy] for cy in Wy if cy > 0)
+    Fbot, Ftop = axis_law(Lx, ex, wall_u[0]), axis_law(Lx, ex, wall_u[1])
+    nodes = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)]
+    f = dict(f0)
+    for _ in range(steps):
+        post = {}
+        for x, y, z in nodes:
+            vals = [(c, f[(x, y, z) + c]) for c in vel]
+            rho = sum(v for _, v in vals)
+            u = [sum(v * c[d] for c, v in vals) / rho for d in range(3)]
+            ex_, ey_, ez_ = axis_law(Lx, ex, u[0]), axis_law(Ly, ey, u[1]), axis_law(Lz, ez, u[2])
+            for c, v in vals:
+                feq = rho * ex_[c[0]] * ey_[c[1]] * ez_[c[2]]
+                force = Wx[c[0]] * Wy[c[1]] * Wz[c[2]] * c[0] * g / thx
+                post[(x, y, z) + c] = v + omega * (feq - v) + force
+        new = {}
+        absorbed = {"bot": defaultdict(float), "top": defaultdict(float)}
+        for (x, y, z, cx, cy, cz), v in post.items():
+            xd, yd, zd = (x + cx) % nx, y + cy, (z + cz) % nz
+            if bc_y == WALL and yd < 0:
+                absorbed["bot"][(xd, zd)] += v
+                continue
+            if bc_y == WALL and yd >= ny:
+                absorbed["top"][(xd, zd)] += v
+                continue
+            new[(xd, yd % ny, zd, cx, cy, cz)] = v
+        if bc_y == WALL:
+            for z in range(nz):
+                for x in range(nx):
+                    for cx, cy, cz in vel:
+                        if cy > 0:
+                            for y in range(cy):
+                                new[(x, y, z, cx, cy, cz)] = absorbed["bot"][(x, z)] / jplus * Fbot[cx] * Wy[cy] * Wz[cz]
+                        elif cy < 0:
+                            for y in range(ny + cy, ny):
+                                new[(x, y, z, cx, cy, cz)] = absorbed["top"][(x, z)] / jplus * Ftop[cx] * Wy[cy] * Wz[cz]
+        assert len(new) == len(vel) * nx * ny * nz
+        f = new
+    return f
+
+
+def to_dict3(arr, Lx, Ly, Lz, even=(False, False, False)):
+    """[q][z][y][x] array, q = (c*Qy + b)*Qx + a -> dict keyed by (x, y, z, cx, cy, cz)."""
+    vx, vy, vz = axis_velocities(Lx, even[0]), axis_velocities(Ly, even[1]), axis_velocities(Lz, even[2])
+    Q, nz, ny, nx = arr.shape
+    out = {}
+    for q in range(Q):
+        cb, a = divmod(q, len(vx))
+        c, b = divmod(cb, len(vy))
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    out[(x, y, z, vx[a], vy[b], vz[c])] = float(arr[q, z, y, x])
+    return out
+
+
+def from_dict3(d, Lx, Ly, Lz, nx, ny, nz, even=(False, False, False)):
+    import numpy as np
+
+    vx, vy, vz = axis_velocities(Lx, even[0]), axis_velocities(Ly, even[1]), axis_velocities(Lz, even[2])
+    ix = {c: i for i, c in enumerate(vx)}
+    iy = {c: i for i, c in enumerate(vy)}
+    iz = {c: i for i, c in enumerate(vz)}
+    arr = np.zeros((len(vx) * len(vy) * len(vz), nz, ny, nx))
+    for (x, y, z, cx, cy, cz), v in d.items():
+        arr[(iz[cz] * len(vy) + iy[cy]) * len(vx) + ix[cx], z, y, x] = v
+    return arr
