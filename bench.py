@@ -90,6 +90,26 @@ def run_gpu(level: int, nx: int, ny: int, storage: str, steps: int, warmup: int,
     return out
 
 
+def run_gpu3(levels, even_y: bool, nx: int, ny: int, nz: int, storage: str, steps: int, warmup: int):
+    """A three-dimensional lattice (periodic x, z; walls across y), force-driven
+    from rest, timed like run_gpu."""
+    from paper_1905_04597_amd import glbm
+
+    lx, ly, lz = levels
+    cfg = glbm.make_config(3, lx, ly, nx, ny, kn=0.1, bc_y="wall", g=1e-5, storage=storage, even_y=even_y,
+                           level_z=lz, nz=nz)
+    s = glbm.Solver(cfg)
+    s.init_fields()
+    gpu_s, _ = time_steps(s, steps, warmup)
+    nodes = nx * ny * nz
+    per_step = gpu_s / steps
+    algo = 2 * s.Q * ELEM_BYTES[storage] * nodes
+    s.close()
+    return {"lattice": "3d", "levels": list(levels), "even_y": even_y, "shape": [nx, ny, nz], "Q": s.Q,
+            "glups": round(nodes * steps / gpu_s / 1e9, 4), "ms_per_step": round(per_step * 1e3, 4),
+            "achieved_GBs": round(algo / per_step / 1e9, 1), "frac": round(algo / per_step / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def copy_probe(nbytes: int = 2 << 30, reps: int = 10):
     """A plain device copy of known size: the achievable read + write rate on
     this GPU (context for the roofline) and a known-size kernel for
@@ -371,6 +391,10 @@ def main(argv=None):
                 sweep.append({"lattice": lattice, "N": lv, "Q": r["Q"], "glups": round(r["glups"], 4),
                               "achieved_GBs": round(r["achieved_GBs"], 4), "ms_per_step": round(r["ms_per_step"], 4),
                               "frac": round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)})
+        # three dimensions: D3Q27, G-D3Q125, D1Q3 x G-D1Q7 (or Q8) x D1Q3
+        for levels, ev, shape in (((1, 1, 1), False, (256, 256, 128)), ((2, 2, 2), False, (128, 128, 128)),
+                                  ((1, 3, 1), False, (256, 128, 128)), ((1, 3, 1), True, (256, 128, 128))):
+            sweep.append(run_gpu3(levels, ev, *shape, a.storage, a.sweep_steps, 5))
     batched = None if a.no_batched else run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)
     served = None if a.no_served else run_served(a.served_seconds)
     solves = None if a.no_served else run_solves()

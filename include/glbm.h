@@ -80,7 +80,7 @@ extern "C" {
                             products (N = 1..6). */
 
 typedef struct glbm_config {
-    int32_t dims;     /* 1 or 2 */
+    int32_t dims;     /* 1, 2 or 3 */
     int32_t level_x;  /* hierarchy level N of the x axis, 1..GLBM_MAX_LEVEL */
     int32_t level_y;  /* level of the y axis (two dimensions), 1..GLBM_MAX_LEVEL; ignored in 1D */
     int32_t storage;  /* GLBM_STORE_* */
@@ -96,6 +96,14 @@ typedef struct glbm_config {
     double g;         /* body force along x: momentum added per node and step */
     int32_t kind_x;   /* GLBM_AXIS_ODD or GLBM_AXIS_EVEN */
     int32_t kind_y;   /* GLBM_AXIS_ODD or GLBM_AXIS_EVEN (two dimensions); ignored in 1D */
+    /* Three dimensions (dims = 3): the tensor product of three axes (section 4
+     * with a third factor), periodic in x and z, periodic or walls in y.
+     * Built: D3Q27 (levels 1,1,1), G-D3Q125 (2,2,2), D1Q3 x G-D1Q(2N+1) x D1Q3
+     * (1,N,1, N = 2, 3) and D1Q3 x G-D1Q(2N+2) x D1Q3 (1,N,1 with kind_y EVEN,
+     * N = 2, 3).  Ignored in one and two dimensions. */
+    int64_t nz;       /* nodes along z (>= the fastest z velocity) */
+    int32_t level_z;  /* level of the z axis, 1..GLBM_MAX_LEVEL */
+    int32_t kind_z;   /* GLBM_AXIS_ODD or GLBM_AXIS_EVEN */
 } glbm_config;
 
 /* Global diagnostics, FP64 sums over all nodes (glbm_stats). */
@@ -113,6 +121,7 @@ typedef struct glbm_stats {
     double nonpositive_nodes; /* nodes with u^2 above 2 N theta0 on some axis (theta0 of the
                                  underlying 2N+1 walk: N/3, or 4N/3 on an even axis's half grid)
                                  (equilibrium not positive, section 3) */
+    double momentum_z;      /* sum of f(t) c_z (three dimensions; 0 otherwise) */
 } glbm_stats_t;
 
 typedef struct glbm_solver glbm_t;
@@ -154,7 +163,17 @@ int glbm_step(glbm_t *h, int64_t nsteps);
  * be NULL (skipped). */
 int glbm_moments(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *pxy);
 
-/* Copy f(t) (pre-collision, FP32, canonical [Q][ny][nx]) into device memory. */
+/* As glbm_init_fields, with the z velocity uz (three dimensions; may be NULL).
+ * Fields are [nz][ny][nx]. */
+int glbm_init_fields3(glbm_t *h, const float *rho, const float *ux, const float *uy, const float *uz);
+
+/* As glbm_moments, with the z velocity uz (written in three dimensions only;
+ * the temperature is then per degree of freedom over three axes).  Fields are
+ * [nz][ny][nx]; any pointer may be NULL. */
+int glbm_moments3(glbm_t *h, float *rho, float *ux, float *uy, float *uz, float *T, float *pxy);
+
+/* Copy f(t) (pre-collision, FP32, canonical [Q][nz][ny][nx], q = (c Qy + b) Qx
+ * + a) into device memory. */
 int glbm_get_populations(glbm_t *h, float *out);
 
 /* Global FP64 diagnostics at the current time.  Synchronizes the stream.  The

@@ -38,7 +38,7 @@ def _hipcc() -> str:
 
 
 def _deps(src: str):
-    common = [os.path.join(CSRC, f) for f in ("glbm_device.h", "glbm_internal.h")]
+    common = [os.path.join(CSRC, f) for f in ("glbm_device.h", "glbm_internal.h", "glbm_device3.h")]
     if src.endswith("glbm_api.hip"):
         common.append(os.path.join(os.path.dirname(HERE), "include", "glbm.h"))
     return [src] + common
@@ -62,7 +62,10 @@ def _compile(args):
 
 def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    tasks = [(os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), [])]
+    # the three-dimensional objects are among the slowest: start them first
+    tasks = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3%s.o" % ("c" if c else "")),
+              ["-DGLBM3_COMPACT=%d" % c]) for c in (0, 1)]
+    tasks.append((os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), []))
     for lv in LEVELS:
         for even in (0, 1):
             for compact in (0, 1):

@@ -14,6 +14,8 @@
 #include "../../include/glbm.h"
 #include "glbm_internal.h"
 
+#include <map>
+
 using namespace glbm;
 
 namespace {
@@ -39,11 +41,15 @@ int hip_fail(hipError_t e, const char *what)
 Variant g_variants[kAxisCodes][kAxisCodes][4][3][2];
 std::once_flag g_once;
 
+std::map<long long, Variant> g_variants3;
+
 void register_all()
 {
 #define GLBM_CALL_REGISTER(E, C, L) register_##E##_##C##_##L();
     GLBM_OBJECTS(GLBM_CALL_REGISTER)
 #undef GLBM_CALL_REGISTER
+    register3_padded();
+    register3_compact();
 }
 
 // Host copy of the per-axis equilibrium at rho = 1 (N-fold convolution of the
@@ -102,31 +108,38 @@ void host_axis_equilibrium(const HostAxis &ax, double u, double *F)
 }
 
 struct Geometry {
-    HostAxis x, y;
+    HostAxis x, y, z;
     int q, eb;
     int bcx;  // kernel variant's x boundary and row layout (BcX)
-    int64_t nx, ny, nxp;
+    int64_t nx, ny, nz, nxp;  // rows are numbered z ny + y
     uint64_t plane_bytes, buf_bytes;
 };
 
 int check_config(const glbm_config *c, Geometry *g)
 {
     if (!c) return fail(GLBM_ERR_INVALID, "config is NULL");
-    if (c->dims != 1 && c->dims != 2) return fail(GLBM_ERR_INVALID, "dims must be 1 or 2 (got %d)", c->dims);
-    const int lx = c->level_x, ly = c->dims == 2 ? c->level_y : 0;
+    if (c->dims < 1 || c->dims > 3) return fail(GLBM_ERR_INVALID, "dims must be 1, 2 or 3 (got %d)", c->dims);
+    const int lx = c->level_x, ly = c->dims >= 2 ? c->level_y : 0, lz = c->dims == 3 ? c->level_z : 0;
     if (lx < 1 || lx > kMaxLevel) return fail(GLBM_ERR_INVALID, "level_x must be in 1..%d", kMaxLevel);
-    if (c->dims == 2 && (ly < 1 || ly > kMaxLevel)) return fail(GLBM_ERR_INVALID, "level_y must be in 1..%d", kMaxLevel);
-    const int kx = c->kind_x, ky = c->dims == 2 ? c->kind_y : GLBM_AXIS_ODD;
-    if ((kx != GLBM_AXIS_ODD && kx != GLBM_AXIS_EVEN) || (ky != GLBM_AXIS_ODD && ky != GLBM_AXIS_EVEN))
+    if (c->dims >= 2 && (ly < 1 || ly > kMaxLevel)) return fail(GLBM_ERR_INVALID, "level_y must be in 1..%d", kMaxLevel);
+    if (c->dims == 3 && (lz < 1 || lz > kMaxLevel)) return fail(GLBM_ERR_INVALID, "level_z must be in 1..%d", kMaxLevel);
+    const int kx = c->kind_x, ky = c->dims >= 2 ? c->kind_y : GLBM_AXIS_ODD, kz = c->dims == 3 ? c->kind_z : GLBM_AXIS_ODD;
+    if ((kx != GLBM_AXIS_ODD && kx != GLBM_AXIS_EVEN) || (ky != GLBM_AXIS_ODD && ky != GLBM_AXIS_EVEN) ||
+        (kz != GLBM_AXIS_ODD && kz != GLBM_AXIS_EVEN))
         return fail(GLBM_ERR_INVALID, "axis kinds must be GLBM_AXIS_ODD or GLBM_AXIS_EVEN");
     const HostAxis ax = host_axis(lx, kx == GLBM_AXIS_EVEN), ay = host_axis(ly, ky == GLBM_AXIS_EVEN);
+    const HostAxis az = host_axis(lz, kz == GLBM_AXIS_EVEN);
     if (c->storage < GLBM_STORE_F32 || c->storage > GLBM_STORE_BF16_SHIFTED_SR)
         return fail(GLBM_ERR_INVALID, "unknown storage %d", c->storage);
-    const int64_t nx = c->nx, ny = c->dims == 2 ? c->ny : 1;
-    if (nx < 1 || ny < 1) return fail(GLBM_ERR_INVALID, "nx and ny must be positive");
+    const int64_t nx = c->nx, ny = c->dims >= 2 ? c->ny : 1, nz = c->dims == 3 ? c->nz : 1;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(GLBM_ERR_INVALID, "nx, ny and nz must be positive");
+    if (c->dims == 3 && c->bc_x != GLBM_BC_PERIODIC)
+        return fail(GLBM_ERR_INVALID, "three-dimensional lattices are periodic in x");
+    if (c->dims == 3 && nz < az.vmax)
+        return fail(GLBM_ERR_INVALID, "nz (%lld) must be at least the fastest z velocity %d", (long long)nz, az.vmax);
     if (c->bc_x != GLBM_BC_PERIODIC && c->bc_x != GLBM_BC_EQ_ENDS)
         return fail(GLBM_ERR_INVALID, "bc_x must be periodic or equilibrium ends");
-    const int bcy = c->dims == 2 ? c->bc_y : GLBM_BC_PERIODIC;
+    const int bcy = c->dims >= 2 ? c->bc_y : GLBM_BC_PERIODIC;
     if (bcy != GLBM_BC_PERIODIC && bcy != GLBM_BC_WALL)
         return fail(GLBM_ERR_INVALID, "bc_y must be periodic or wall");
     if (c->bc_x == GLBM_BC_EQ_ENDS && bcy == GLBM_BC_WALL)
@@ -136,25 +149,27 @@ int check_config(const glbm_config *c, Geometry *g)
     if (bcy == GLBM_BC_WALL && ny < 2 * ay.vmax)
         return fail(GLBM_ERR_INVALID, "ny (%lld) must be at least 2*%d (twice the fastest y velocity) with walls",
                     (long long)ny, ay.vmax);
-    if (c->dims == 2 && bcy == GLBM_BC_PERIODIC && ny < ay.vmax)
+    if (c->dims >= 2 && bcy == GLBM_BC_PERIODIC && ny < ay.vmax)
         return fail(GLBM_ERR_INVALID, "periodic ny (%lld) must be at least the fastest y velocity %d", (long long)ny,
                     ay.vmax);
     if (c->bc_x == GLBM_BC_EQ_ENDS && nx < ax.vmax)
         return fail(GLBM_ERR_INVALID, "nx must be at least the fastest x velocity with equilibrium ends");
     g->x = ax;
     g->y = ay;
-    g->q = ax.q * ay.q;
+    g->z = az;
+    g->q = ax.q * ay.q * az.q;
     g->eb = (c->storage == GLBM_STORE_BF16_SHIFTED || c->storage == GLBM_STORE_BF16_SHIFTED_SR) ? 2 : 4;
     g->nx = nx;
     g->ny = ny;
+    g->nz = nz;
     // periodic x narrower than a wave: compact rows of nx columns (node x at
     // column x); otherwise padded rows with ghosts (node x at column kGhost + x)
-    const bool compact = c->dims == 2 && c->bc_x == GLBM_BC_PERIODIC && nx < kCompactBelow;
+    const bool compact = c->dims >= 2 && c->bc_x == GLBM_BC_PERIODIC && nx < kCompactBelow;
     g->bcx = compact ? BCX_WRAP : c->bc_x == GLBM_BC_EQ_ENDS ? BCX_EQ : BCX_PERIODIC;
     g->nxp = compact ? nx : (kGhost + nx + ax.vmax + 63) / 64 * 64;
-    g->plane_bytes = ((uint64_t)(ny * g->nxp) * g->eb + 255) & ~(uint64_t)255;
+    g->plane_bytes = ((uint64_t)(nz * ny * g->nxp) * g->eb + 255) & ~(uint64_t)255;
     g->buf_bytes = (g->plane_bytes * g->q + 255) & ~(uint64_t)255;
-    if (nx * ny > (int64_t)0x7fffffff / 4) return fail(GLBM_ERR_INVALID, "too many nodes");
+    if (nx * ny * nz > (int64_t)0x7fffffff / 4) return fail(GLBM_ERR_INVALID, "too many nodes");
     if (g->buf_bytes >= ((uint64_t)1 << 32))
         return fail(GLBM_ERR_INVALID, "population buffer of %llu bytes exceeds 4 GiB", (unsigned long long)g->buf_bytes);
     return GLBM_OK;
@@ -185,6 +200,12 @@ namespace glbm {
 Variant *variant_slot(int ax, int ay, int storage, int bcx, int bcy)
 {
     return &g_variants[ax][ay][storage][bcx][bcy];
+}
+
+Variant *variant3_slot(int ax, int ay, int az, int storage, int bcx, int bcy)
+{
+    const long long key = ((((long long)ax * kAxisCodes + ay) * kAxisCodes + az) * 4 + storage) * 6 + bcx * 2 + bcy;
+    return &g_variants3[key];
 }
 }  // namespace glbm
 
@@ -228,8 +249,8 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
 
     double tau = cfg->tau;
     if (!(tau > 0.0)) {
-        const double H = cfg->dims == 2 ? (double)g.ny : (double)g.nx;
-        const double theta = cfg->dims == 2 ? g.y.theta : g.x.theta;
+        const double H = cfg->dims >= 2 ? (double)g.ny : (double)g.nx;
+        const double theta = cfg->dims >= 2 ? g.y.theta : g.x.theta;
         if (!(cfg->kn > 0.0)) return fail(GLBM_ERR_INVALID, "either tau > 0 or kn > 0 is required");
         tau = cfg->kn * H / sqrt(2.0 * theta);  // Eq. kn with nu = theta tau
     }
@@ -237,11 +258,12 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     if (!(omega > 0.0 && omega < 2.0)) return fail(GLBM_ERR_INVALID, "collision frequency %g outside (0, 2)", omega);
 
     std::call_once(g_once, register_all);
-    const int bcy = cfg->dims == 2 ? cfg->bc_y : GLBM_BC_PERIODIC;
-    const Variant *v = variant_slot(g.x.code, g.y.code, cfg->storage, g.bcx, bcy);
+    const int bcy = cfg->dims >= 2 ? cfg->bc_y : GLBM_BC_PERIODIC;
+    const Variant *v = cfg->dims == 3 ? variant3_slot(g.x.code, g.y.code, g.z.code, cfg->storage, g.bcx, bcy)
+                                      : variant_slot(g.x.code, g.y.code, cfg->storage, g.bcx, bcy);
     if (!v->step)
-        return fail(GLBM_ERR_UNSUPPORTED, "no kernels built for axes (%s%d, %s%d) with these boundaries",
-                    g.x.even ? "even " : "", g.x.N, g.y.even ? "even " : "", g.y.N);
+        return fail(GLBM_ERR_UNSUPPORTED, "no kernels built for axes (%s%d, %s%d, %s%d) with these boundaries",
+                    g.x.even ? "even " : "", g.x.N, g.y.even ? "even " : "", g.y.N, g.z.even ? "even " : "", g.z.N);
 
     glbm_solver *h = new (std::nothrow) glbm_solver();
     if (!h) return fail(GLBM_ERR_INVALID, "out of host memory");
@@ -259,7 +281,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     h->var = v;
     (void)hipGetDevice(&h->device);
 
-    const int64_t nodes = g.nx * g.ny;
+    const int64_t nodes = g.nx * g.ny * g.nz;
     h->grid = (int)((nodes + kBlock - 1) / kBlock);
     KArgs &a = h->base;
     memset(&a, 0, sizeof a);
@@ -267,6 +289,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     a.plane_bytes = (uint32_t)g.plane_bytes;
     a.nx = (int32_t)g.nx;
     a.ny = (int32_t)g.ny;
+    a.nz = (int32_t)g.nz;
     a.nxp = (int32_t)g.nxp;
     a.nodes = (int32_t)nodes;
     a.remap = 1;
@@ -295,7 +318,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     return GLBM_OK;
 }
 
-static int do_init(glbm_t *h, const float *rho, const float *ux, const float *uy, const float *f0)
+static int do_init(glbm_t *h, const float *rho, const float *ux, const float *uy, const float *uz, const float *f0)
 {
     if (!h) return fail(GLBM_ERR_INVALID, "handle is NULL");
     KArgs a = h->base;
@@ -312,6 +335,7 @@ static int do_init(glbm_t *h, const float *rho, const float *ux, const float *uy
     a.i_rho = rho;
     a.i_ux = ux;
     a.i_uy = uy;
+    a.i_uz = uz;
     a.i_f = f0;
     a.seed = step_seed(0);
     e = h->var->init(a, h->grid, h->stream);
@@ -324,13 +348,18 @@ static int do_init(glbm_t *h, const float *rho, const float *ux, const float *uy
 
 int glbm_init_fields(glbm_t *h, const float *rho, const float *ux, const float *uy)
 {
-    return do_init(h, rho, ux, uy, nullptr);
+    return do_init(h, rho, ux, uy, nullptr, nullptr);
+}
+
+int glbm_init_fields3(glbm_t *h, const float *rho, const float *ux, const float *uy, const float *uz)
+{
+    return do_init(h, rho, ux, uy, uz, nullptr);
 }
 
 int glbm_init_populations(glbm_t *h, const float *f0)
 {
     if (!f0) return fail(GLBM_ERR_INVALID, "f0 is NULL");
-    return do_init(h, nullptr, nullptr, nullptr, f0);
+    return do_init(h, nullptr, nullptr, nullptr, nullptr, f0);
 }
 
 int glbm_step(glbm_t *h, int64_t nsteps)
@@ -352,7 +381,7 @@ int glbm_step(glbm_t *h, int64_t nsteps)
     return GLBM_OK;
 }
 
-static int observe(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *pxy, float *f)
+static int observe(glbm_t *h, float *rho, float *ux, float *uy, float *uz, float *T, float *pxy, float *f)
 {
     if (!h) return fail(GLBM_ERR_INVALID, "handle is NULL");
     if (!h->ready) return fail(GLBM_ERR_STATE, "moments before init");
@@ -364,6 +393,7 @@ static int observe(glbm_t *h, float *rho, float *ux, float *uy, float *T, float 
     a.o_rho = rho;
     a.o_ux = ux;
     a.o_uy = uy;
+    a.o_uz = uz;
     a.o_T = T;
     a.o_pxy = pxy;
     a.o_f = f;
@@ -374,13 +404,18 @@ static int observe(glbm_t *h, float *rho, float *ux, float *uy, float *T, float 
 
 int glbm_moments(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *pxy)
 {
-    return observe(h, rho, ux, uy, T, pxy, nullptr);
+    return observe(h, rho, ux, uy, nullptr, T, pxy, nullptr);
+}
+
+int glbm_moments3(glbm_t *h, float *rho, float *ux, float *uy, float *uz, float *T, float *pxy)
+{
+    return observe(h, rho, ux, uy, uz, T, pxy, nullptr);
 }
 
 int glbm_get_populations(glbm_t *h, float *out)
 {
     if (!out) return fail(GLBM_ERR_INVALID, "out is NULL");
-    return observe(h, nullptr, nullptr, nullptr, nullptr, nullptr, out);
+    return observe(h, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, out);
 }
 
 int glbm_stats(glbm_t *h, glbm_stats_t *out)
@@ -425,6 +460,7 @@ int glbm_stats(glbm_t *h, glbm_stats_t *out)
     out->wall_mass[1] = s[8];
     out->wall_momentum[1] = s[9];
     out->nonpositive_nodes = s[10];
+    out->momentum_z = s[11];
     return GLBM_OK;
 }
 
@@ -554,6 +590,7 @@ static int check_members(glbm_t *const *members, int32_t n, const glbm_batch *se
         glbm_solver *m = members[i];
         if (!m) return fail(GLBM_ERR_INVALID, "member %d is NULL", i);
         if (!m->ready) return fail(GLBM_ERR_STATE, "member %d is not initialised", i);
+        if (!m->var->batch) return fail(GLBM_ERR_UNSUPPORTED, "member %d: batches take one- and two-dimensional lattices", i);
         const bool mine = self && std::find(self->members.begin(), self->members.end(), m) != self->members.end();
         if (m->in_batch && !mine) return fail(GLBM_ERR_STATE, "member %d already belongs to a batch", i);
         for (int j = 0; j < i; ++j)

@@ -39,7 +39,7 @@ namespace glbm {
 constexpr int kMaxLevel = 7;
 constexpr int kMaxQ1 = 2 * kMaxLevel + 2;  // velocities of the largest axis
 constexpr int kBlock = 256;
-constexpr int kNumStats = 11;
+constexpr int kNumStats = 12;
 constexpr int kGhost = 64;  // padded column of node x = 0 (>= the largest level)
 constexpr int kCompactBelow = 64;  // periodic-x lattices narrower than this use compact rows
 
@@ -305,7 +305,8 @@ struct KArgs {
     void *dst;            // destination of f*(t)
     uint32_t buf_bytes;   // bytes of one population buffer
     uint32_t plane_bytes; // bytes of one velocity plane (ny * nxp elements)
-    int32_t nx, ny, nxp;  // nodes per axis, padded row length (multiple of 64, >= G + nx + LX)
+    int32_t nx, ny, nxp;  // nodes per axis, row length (padded: a multiple of 64 with ghosts; compact: nx)
+    int32_t nz;           // nodes along z (three dimensions; 1 otherwise)
     int32_t nodes;        // nx * ny
     int32_t remap;        // XCD-aware block order
     int32_t local;        // observe kernel: read f(t) at the node, no streaming
@@ -316,6 +317,7 @@ struct KArgs {
     double fwsum[2];      // sum_a fw_a of the FP32 table (exact, in double)
     // observe outputs (canonical [y][x] / [q][y][x], may be null)
     float *o_rho, *o_ux, *o_uy, *o_T, *o_pxy, *o_f;
+    float *o_uz;          // three dimensions
     // stats
     const void *prev;     // f*(t-1) for the residual (null at t = 0)
     float g;
@@ -323,6 +325,7 @@ struct KArgs {
     double *partials;     // [gridDim][kNumStats]
     // init
     const float *i_rho, *i_ux, *i_uy, *i_f;
+    const float *i_uz;    // three dimensions
     void *dst2;           // init: buffer receiving f(0)
 };
 
@@ -1094,6 +1097,7 @@ __global__ __launch_bounds__(kBlock) void ends_kernel(KArgs p, float rho_left, f
 // [0] mass  [1] momentum x  [2] momentum y  [3] energy (post)  [4] sum u_x^2
 // [5] sum (u_x(t) - u_x(t-1))^2  [6] bottom absorbed mass  [7] bottom x momentum
 // [8] top absorbed mass  [9] top x momentum  [10] non-positive nodes
+// [11] momentum z (three dimensions)
 template <int LX, int LY, int ST, int BCX, int BCY>
 __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
 {

@@ -1,0 +1,558 @@
+// Three-dimensional lattices: the tensor product of three axes (section 4,
+// f^eq = rho F_a(u_x) F_b(u_y) F_c(u_z)), periodic in x and z, periodic or
+// diffuse walls across y (the reading of sections 5.3-5.4 with the wall
+// density per (x, z) column).
+//
+// Layout: velocity planes [q][z][y][row], q = (c QY + b) QX + a; a row is the
+// padded or compact x row of the two-dimensional lattices (XAddr), rows are
+// numbered z ny + y.  One lane owns one node and holds its Q populations in
+// FP32 registers (every storage); the node's steps are those of the 2D
+// kernels with a third factor in the equilibrium, the force shape, the wall
+// emission and the mass / momentum defect correction.
+#pragma once
+
+#include "glbm_device.h"
+
+namespace glbm {
+
+template <int LX, int LY, int LZ, int ST>
+struct Lat3 {
+    static constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q, QZ = Axis<LZ>::Q, Q = QX * QY * QZ;
+    static constexpr int EB = Elem<ST>::bytes;
+    static constexpr bool shifted = Elem<ST>::shifted;
+    template <int a, int b, int c>
+    static constexpr int q() { return (c * QY + b) * QX + a; }
+};
+
+// Shift of the shifted storages in three dimensions: S_abc ~ W_a W_b W_c on
+// the 2^-24 grid, the remainder shared equally by the slowest populations
+// (as ShiftTable), and the moments of S the kernels add back.
+template <int LX, int LY, int LZ>
+struct ShiftTable3 {
+    static constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q, QZ = Axis<LZ>::Q;
+    float s[QZ][QY][QX];
+    float sum, sxx, syy, szz;
+    float absorbed;  // sum of S over the populations one wall absorbs per column
+    constexpr ShiftTable3() : s{}, sum(0.0f), sxx(0.0f), syy(0.0f), szz(0.0f), absorbed(0.0f)
+    {
+        long long q[QZ][QY][QX] = {};
+        long long tot = 0;
+        for (int c = 0; c < QZ; ++c)
+            for (int b = 0; b < QY; ++b)
+                for (int a = 0; a < QX; ++a)
+                    tot += (q[c][b][a] = snap(kRest<LX>.w[a] * kRest<LY>.w[b] * kRest<LZ>.w[c]));
+        const long long m = (Axis<LX>::even ? 2 : 1) * (Axis<LY>::even ? 2 : 1) * (Axis<LZ>::even ? 2 : 1);
+        const long long rem = (long long)kGrid - tot;
+        const long long share = rem >= 0 ? rem / m : -((-rem + m - 1) / m);
+        long long all = 0, xx = 0, yy = 0, zz = 0, ab = 0;
+        for (int c = 0; c < QZ; ++c)
+            for (int b = 0; b < QY; ++b)
+                for (int a = 0; a < QX; ++a) {
+                    const long long ca = Axis<LX>::c(a), cb = Axis<LY>::c(b), cc = Axis<LZ>::c(c);
+                    if ((ca < 0 ? -ca : ca) == Axis<LX>::cmin && (cb < 0 ? -cb : cb) == Axis<LY>::cmin &&
+                        (cc < 0 ? -cc : cc) == Axis<LZ>::cmin)
+                        q[c][b][a] += share;
+                    all += q[c][b][a];
+                    xx += q[c][b][a] * ca * ca;
+                    yy += q[c][b][a] * cb * cb;
+                    zz += q[c][b][a] * cc * cc;
+                    if (cb < 0) ab += q[c][b][a] * (-cb);
+                    s[c][b][a] = (float)(q[c][b][a] / kGrid);
+                }
+        sum = (float)(all / kGrid);
+        sxx = (float)(xx / kGrid);
+        syy = (float)(yy / kGrid);
+        szz = (float)(zz / kGrid);
+        absorbed = (float)(ab / kGrid);
+    }
+};
+
+template <int LX, int LY, int LZ>
+inline constexpr ShiftTable3<LX, LY, LZ> kShift3{};
+
+// Rest weights of the (y, z) pair in FP32, and the half flux of the y axis
+// weighted by them: the wall emits rho_w fw_a W_bc into |c_b| rows, i.e.
+// rho_w * sum_a fw_a * J3 per column.
+template <int LY, int LZ>
+struct YZWeights {
+    float w[Axis<LZ>::Q][Axis<LY>::Q];
+    double jplus;
+    constexpr YZWeights() : w{}, jplus(0.0)
+    {
+        for (int c = 0; c < Axis<LZ>::Q; ++c)
+            for (int b = 0; b < Axis<LY>::Q; ++b) {
+                w[c][b] = (float)(kRest<LY>.w[b] * kRest<LZ>.w[c]);
+                if (Axis<LY>::c(b) > 0) jplus += Axis<LY>::c(b) * (double)w[c][b];
+            }
+    }
+};
+
+template <int LY, int LZ>
+inline constexpr YZWeights<LY, LZ> kYZ{};
+
+template <int LZ>
+__device__ __forceinline__ int wrap_z(int zs, int nz)
+{
+    // nz >= the fastest z velocity: one correction at most
+    return zs < 0 ? zs + nz : zs >= nz ? zs - nz : zs;
+}
+
+// Mass absorbed by a diffuse wall in column (x, z): the post-collision
+// populations leaving through the wall in this streaming that would land in
+// (x, z) (sources at x - c_x, z - c_z in the rows within reach).
+template <int LX, int LY, int LZ, int ST, int BCX, bool BOTTOM>
+__device__ __forceinline__ float wall_absorbed3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa,
+                                                int z, float *mom)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    float s = 0.0f, m = 0.0f;
+    unroll<L::QZ>([&](auto C) {
+        constexpr int c = C, cc = Axis<LZ>::c(c);
+        const int zs = wrap_z<LZ>(z - cc, p.nz);
+        unroll<L::QY>([&](auto B) {
+            constexpr int b = B, cb = Axis<LY>::c(b);
+            if constexpr ((BOTTOM && cb < 0) || (!BOTTOM && cb > 0)) {
+                constexpr int depth = cb < 0 ? -cb : cb;
+                unroll<depth>([&](auto R) {
+                    const int row = BOTTOM ? (int)R : p.ny - 1 - (int)R;
+                    const uint32_t rowb = row_bytes<L::EB>(p, zs * p.ny + row);
+                    unroll<L::QX>([&](auto A) {
+                        constexpr int a = A, ca = Axis<LX>::c(a);
+                        const float v = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)L::template q<a, b, c>() * p.plane_bytes);
+                        s += v;
+                        if (mom) m = __builtin_fmaf((float)ca, v, m);
+                    });
+                });
+            }
+        });
+    });
+    if (mom) *mom = m;
+    if constexpr (L::shifted) s += kShift3<LX, LY, LZ>.absorbed;
+    return s;
+}
+
+// Pre-collision populations of node (x, y, z): pulled, or emitted by a wall.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y, int z,
+                                      float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q])
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    float rw[2] = {0.0f, 0.0f};
+    if constexpr (BCY == BCY_WALL) {
+        constexpr double jp = kYZ<LY, LZ>.jplus;
+        constexpr int reach = Axis<LY>::vmax;
+        if (y < reach) rw[0] = wall_absorbed3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z, nullptr) / (float)(jp * p.fwsum[0]);
+        if (y >= p.ny - reach)
+            rw[1] = wall_absorbed3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z, nullptr) / (float)(jp * p.fwsum[1]);
+    }
+    unroll<L::QZ>([&](auto C) {
+        constexpr int c = C, cc = Axis<LZ>::c(c);
+        const int zs = wrap_z<LZ>(z - cc, p.nz);
+        unroll<L::QY>([&](auto B) {
+            constexpr int b = B, cb = Axis<LY>::c(b);
+            int ys = y - cb;
+            bool emit = false;
+            if constexpr (BCY == BCY_WALL) {
+                if constexpr (cb > 0) emit = ys < 0;
+                if constexpr (cb < 0) emit = ys >= p.ny;
+            } else {
+                if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
+                if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
+            }
+            if (emit) {
+                constexpr int side = cb > 0 ? 0 : 1;
+                const float rwb = rw[side] * kYZ<LY, LZ>.w[c][b];
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A;
+                    if constexpr (L::shifted)
+                        v[c][b][a] = __builtin_fmaf(rwb, p.fw[side][a], -kShift3<LX, LY, LZ>.s[c][b][a]);
+                    else
+                        v[c][b][a] = rwb * p.fw[side][a];
+                });
+            } else {
+                const uint32_t rowb = row_bytes<L::EB>(p, zs * p.ny + ys);
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A;
+                    v[c][b][a] = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)L::template q<a, b, c>() * p.plane_bytes);
+                });
+            }
+        });
+    });
+}
+
+// BGK collision with the linear force (section 5.4) on FP32 working values,
+// with the conservative defect correction of the two-dimensional collide:
+// the FP32 tables rho F_a and F_b F_c carry the mass and momentum only up to
+// rounding; the exact (FP64) sums give the defect, which the slowest
+// populations take out.
+template <int LX, int LY, int LZ, int ST>
+__device__ __forceinline__ void collide3(const KArgs &p, float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q], float rho,
+                                         float jx, float jy, float jz, float ux, float uy, float uz)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    const float om = p.omega;
+    float rF[L::QX], gK[L::QX], FYZ[L::QZ][L::QY];
+    double sx = 0.0, mx = 0.0, syz = 0.0, my = 0.0, mz = 0.0;
+    {
+        double Fd[L::QX];
+        axis_equilibrium<LX, double>((double)ux, Fd);
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, ca = Axis<LX>::c(a);
+            rF[a] = (float)((double)rho * Fd[a]);
+            sx += (double)rF[a];
+            mx += (double)ca * (double)rF[a];
+            gK[a] = p.gth * (float)(kRest<LX>.w[a] * ca);
+        });
+    }
+    {
+        double Fy[L::QY], Fz[L::QZ];
+        axis_equilibrium<LY, double>((double)uy, Fy);
+        axis_equilibrium<LZ, double>((double)uz, Fz);
+        unroll<L::QZ>([&](auto C) {
+            constexpr int c = C, cc = Axis<LZ>::c(c);
+            unroll<L::QY>([&](auto B) {
+                constexpr int b = B, cb = Axis<LY>::c(b);
+                FYZ[c][b] = (float)(Fy[b] * Fz[c]);
+                syz += (double)FYZ[c][b];
+                my += (double)cb * (double)FYZ[c][b];
+                mz += (double)cc * (double)FYZ[c][b];
+            });
+        });
+    }
+    constexpr int nxm = Axis<LX>::cmin ? 2 : 1, nym = Axis<LY>::cmin ? 2 : 1, nzm = Axis<LZ>::cmin ? 2 : 1;
+    const float dm = (float)(sx * syz - (double)rho) * (1.0f / (nxm * nym * nzm));
+    const float hx = (float)(0.5 * (mx * syz - (double)jx)) * (1.0f / (nym * nzm));
+    const float hy = (float)(0.5 * (sx * my - (double)jy)) * (1.0f / (nxm * nzm));
+    const float hz = (float)(0.5 * (sx * mz - (double)jz)) * (1.0f / (nxm * nym));
+    unroll<L::QZ>([&](auto C) {
+        constexpr int c = C, cc = Axis<LZ>::c(c);
+        constexpr bool zmin = (cc < 0 ? -cc : cc) == Axis<LZ>::cmin;
+        unroll<L::QY>([&](auto B) {
+            constexpr int b = B, cb = Axis<LY>::c(b);
+            constexpr bool ymin = (cb < 0 ? -cb : cb) == Axis<LY>::cmin;
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, ca = Axis<LX>::c(a);
+                constexpr bool xmin = (ca < 0 ? -ca : ca) == Axis<LX>::cmin;
+                const float f = v[c][b][a];
+                float neq;  // f^eq - f
+                if constexpr (L::shifted)
+                    neq = __builtin_fmaf(rF[a], FYZ[c][b], -kShift3<LX, LY, LZ>.s[c][b][a]) - f;
+                else
+                    neq = __builtin_fmaf(rF[a], FYZ[c][b], -f);
+                if constexpr (xmin && ymin && zmin) neq -= dm;
+                if constexpr (ymin && zmin && ca == 1) neq -= hx;
+                if constexpr (ymin && zmin && ca == -1) neq += hx;
+                if constexpr (xmin && zmin && cb == 1) neq -= hy;
+                if constexpr (xmin && zmin && cb == -1) neq += hy;
+                if constexpr (xmin && ymin && cc == 1) neq -= hz;
+                if constexpr (xmin && ymin && cc == -1) neq += hz;
+                v[c][b][a] = __builtin_fmaf(gK[a], kYZ<LY, LZ>.w[c][b], __builtin_fmaf(om, neq, f));
+            });
+        });
+    });
+}
+
+template <int LX, int LY, int LZ, int ST>
+__device__ __forceinline__ void moments3(const float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q], float &rho, float &jx,
+                                         float &jy, float &jz)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    float r = 0.0f;
+    jx = jy = jz = 0.0f;
+    unroll<L::QZ>([&](auto C) {
+        constexpr int c = C, cc = Axis<LZ>::c(c);
+        float rc = 0.0f;
+        unroll<L::QY>([&](auto B) {
+            constexpr int b = B, cb = Axis<LY>::c(b);
+            float rs = 0.0f, rx = 0.0f;
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, ca = Axis<LX>::c(a);
+                rs += v[c][b][a];
+                if constexpr (ca != 0) rx = __builtin_fmaf((float)ca, v[c][b][a], rx);
+            });
+            rc += rs;
+            jx += rx;
+            if constexpr (cb != 0) jy = __builtin_fmaf((float)cb, rs, jy);
+        });
+        r += rc;
+        if constexpr (cc != 0) jz = __builtin_fmaf((float)cc, rc, jz);
+    });
+    rho = L::shifted ? kShift3<LX, LY, LZ>.sum + r : r;
+}
+
+// Store node (x, y, z), replicating edge nodes into the ghost columns of
+// padded periodic rows.
+template <int LX, int LY, int LZ, int ST, int BCX>
+__device__ __forceinline__ void store3(const KArgs &p, rsrc_t rd, int x, int row,
+                                       const float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q], uint32_t h)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    constexpr int V = Axis<LX>::vmax;
+    int pc = x + kGhost;
+    if constexpr (BCX == BCX_WRAP) pc = x;
+    if constexpr (BCX == BCX_PERIODIC) pc = kGhost - V + (x + V) % p.nx;
+    for (; pc < kGhost + p.nx + V; pc += p.nx) {
+        const uint32_t off = (uint32_t)(row * p.nxp + pc) * (uint32_t)L::EB;
+        unroll<L::QZ>([&](auto C) {
+            unroll<L::QY>([&](auto B) {
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, b = B, c = C, q = L::template q<a, b, c>();
+                    uint32_t r = 0;
+                    if constexpr (ST == ST_BF16SR) r = rnd_of<q>(h);
+                    st<ST>(rd, off, (uint32_t)q * p.plane_bytes, v[c][b][a], r);
+                });
+            });
+        });
+        if constexpr (BCX != BCX_PERIODIC) break;
+    }
+}
+
+__device__ __forceinline__ void node_xyz(const KArgs &p, int i, int &x, int &y, int &z)
+{
+    const int r = i / p.nx;
+    x = i - r * p.nx;
+    z = r / p.ny;
+    y = r - z * p.ny;
+}
+
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void step3_kernel(KArgs p)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    const int i = tile_index(p) * kBlock + (int)threadIdx.x;
+    if (i >= p.nodes) return;
+    int x, y, z;
+    node_xyz(p, i, x, y, z);
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
+    const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+    float v[L::QZ][L::QY][L::QX];
+    pull3<LX, LY, LZ, ST, BCX, BCY>(p, rs, xa, y, z, v);
+    float rho, jx, jy, jz;
+    moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
+    const float inv = 1.0f / rho;
+    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv);
+    store3<LX, LY, LZ, ST, BCX>(p, rd, x, z * p.ny + y, v, ST == ST_BF16SR ? node_hash(p.seed, i) : 0u);
+}
+
+// Moments of f(t) (FP64 sums of the stored values), as observe_kernel.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void observe3_kernel(KArgs p)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (i >= p.nodes) return;
+    int x, y, z;
+    node_xyz(p, i, x, y, z);
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+    float v[L::QZ][L::QY][L::QX];
+    if (p.local) {
+        const uint32_t base = xa.own(row_bytes<L::EB>(p, z * p.ny + y));
+        unroll<L::QZ>([&](auto C) {
+            unroll<L::QY>([&](auto B) {
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, b = B, c = C;
+                    v[c][b][a] = ld<ST>(rs, base, (uint32_t)L::template q<a, b, c>() * p.plane_bytes);
+                });
+            });
+        });
+    } else {
+        pull3<LX, LY, LZ, ST, BCX, BCY>(p, rs, xa, y, z, v);
+    }
+    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    unroll<L::QZ>([&](auto C) {
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B, c = C;
+                const double f = v[c][b][a];
+                r += f;
+                jx += Axis<LX>::c(a) * f;
+                jy += Axis<LY>::c(b) * f;
+                jz += Axis<LZ>::c(c) * f;
+            });
+        });
+    });
+    const double rho = L::shifted ? (double)kShift3<LX, LY, LZ>.sum + r : r;
+    const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    double Fx[L::QX], Fy[L::QY], Fz[L::QZ];
+    axis_equilibrium<LX, double>(ux, Fx);
+    axis_equilibrium<LY, double>(uy, Fy);
+    axis_equilibrium<LZ, double>(uz, Fz);
+    double e2 = 0.0, exy = 0.0;
+    unroll<L::QZ>([&](auto C) {
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B, c = C, ca = Axis<LX>::c(a), cb = Axis<LY>::c(b), cc = Axis<LZ>::c(c);
+                double f = v[c][b][a];
+                if constexpr (L::shifted) f += (double)kShift3<LX, LY, LZ>.s[c][b][a];
+                const double dev = f - rho * Fx[a] * Fy[b] * Fz[c];
+                e2 += (ca * ca + cb * cb + cc * cc) * dev;
+                exy += (ca * cb) * dev;
+            });
+        });
+    });
+    if (p.o_rho) p.o_rho[i] = (float)rho;
+    if (p.o_ux) p.o_ux[i] = (float)ux;
+    if (p.o_uy) p.o_uy[i] = (float)uy;
+    if (p.o_uz) p.o_uz[i] = (float)uz;
+    if (p.o_T) p.o_T[i] = (float)((Axis<LX>::theta + Axis<LY>::theta + Axis<LZ>::theta + e2 / rho) / 3.0);
+    if (p.o_pxy) p.o_pxy[i] = (float)exy;
+    if (p.o_f) {
+        unroll<L::QZ>([&](auto C) {
+            unroll<L::QY>([&](auto B) {
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, b = B, c = C;
+                    float f = v[c][b][a];
+                    if constexpr (L::shifted) f += kShift3<LX, LY, LZ>.s[c][b][a];
+                    p.o_f[(size_t)L::template q<a, b, c>() * p.nodes + i] = f;
+                });
+            });
+        });
+    }
+}
+
+// f(0) from fields or populations into dst2, f*(0) into dst.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void init3_kernel(KArgs p)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (i >= p.nodes) return;
+    int x, y, z;
+    node_xyz(p, i, x, y, z);
+    float v[L::QZ][L::QY][L::QX];
+    if (p.i_f) {
+        unroll<L::QZ>([&](auto C) {
+            unroll<L::QY>([&](auto B) {
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, b = B, c = C;
+                    v[c][b][a] = p.i_f[(size_t)L::template q<a, b, c>() * p.nodes + i];
+                });
+            });
+        });
+    } else {
+        const double rho = p.i_rho ? p.i_rho[i] : 1.0;
+        double Fx[L::QX], Fy[L::QY], Fz[L::QZ];
+        axis_equilibrium<LX, double>(p.i_ux ? (double)p.i_ux[i] : 0.0, Fx);
+        axis_equilibrium<LY, double>(p.i_uy ? (double)p.i_uy[i] : 0.0, Fy);
+        axis_equilibrium<LZ, double>(p.i_uz ? (double)p.i_uz[i] : 0.0, Fz);
+        unroll<L::QZ>([&](auto C) {
+            unroll<L::QY>([&](auto B) {
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, b = B, c = C;
+                    v[c][b][a] = (float)(rho * Fx[a] * Fy[b] * Fz[c]);
+                });
+            });
+        });
+    }
+    const uint32_t h = ST == ST_BF16SR ? node_hash(p.seed, i) : 0u;
+    unroll<L::QZ>([&](auto C) {
+        unroll<L::QY>([&](auto B) {
+            unroll<L::QX>([&](auto A) {
+                constexpr int a = A, b = B, c = C;
+                if constexpr (L::shifted) v[c][b][a] -= kShift3<LX, LY, LZ>.s[c][b][a];
+                if constexpr (Elem<ST>::bytes == 2) v[c][b][a] = quantize<ST>(v[c][b][a], rnd_of<L::template q<a, b, c>()>(h));
+            });
+        });
+    });
+    const int row = z * p.ny + y;
+    store3<LX, LY, LZ, ST, BCX>(p, make_rsrc(p.dst2, p.buf_bytes), x, row, v, h);
+    float rho, jx, jy, jz;
+    moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
+    const float inv = 1.0f / rho;
+    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv);
+    store3<LX, LY, LZ, ST, BCX>(p, make_rsrc(p.dst, p.buf_bytes), x, row, v, mix32(h));
+}
+
+// FP64 sums (glbm_stats), as stats_kernel, with the z momentum in slot 11.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void stats3_kernel(KArgs p)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    double acc[kNumStats];
+    for (int k = 0; k < kNumStats; ++k) acc[k] = 0.0;
+    if (i < p.nodes) {
+        int x, y, z;
+        node_xyz(p, i, x, y, z);
+        const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+        const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+        const uint32_t base = xa.own(row_bytes<L::EB>(p, z * p.ny + y));
+        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, e = 0.0;
+        unroll<L::QZ>([&](auto C) {
+            unroll<L::QY>([&](auto B) {
+                unroll<L::QX>([&](auto A) {
+                    constexpr int a = A, b = B, c = C, ca = Axis<LX>::c(a), cb = Axis<LY>::c(b), cc = Axis<LZ>::c(c);
+                    const double f = ld<ST>(rs, base, (uint32_t)L::template q<a, b, c>() * p.plane_bytes);
+                    r += f;
+                    jx += ca * f;
+                    jy += cb * f;
+                    jz += cc * f;
+                    e += (ca * ca + cb * cb + cc * cc) * f;
+                });
+            });
+        });
+        if constexpr (L::shifted) {
+            r += (double)kShift3<LX, LY, LZ>.sum;
+            e += (double)kShift3<LX, LY, LZ>.sxx + (double)kShift3<LX, LY, LZ>.syy + (double)kShift3<LX, LY, LZ>.szz;
+        }
+        const double jx_pre = jx - p.g;
+        const double ux = jx_pre / r, uy = jy / r, uz = jz / r;
+        acc[0] = r;
+        acc[1] = jx_pre;
+        acc[2] = jy;
+        acc[3] = e;
+        acc[4] = ux * ux;
+        acc[11] = jz;
+        if (p.prev) {
+            const rsrc_t rp = make_rsrc(p.prev, p.buf_bytes);
+            double r0 = 0.0, j0 = 0.0;
+            unroll<L::QZ>([&](auto C) {
+                unroll<L::QY>([&](auto B) {
+                    unroll<L::QX>([&](auto A) {
+                        constexpr int a = A, b = B, c = C;
+                        const double f = ld<ST>(rp, base, (uint32_t)L::template q<a, b, c>() * p.plane_bytes);
+                        r0 += f;
+                        j0 += Axis<LX>::c(a) * f;
+                    });
+                });
+            });
+            if constexpr (L::shifted) r0 += (double)kShift3<LX, LY, LZ>.sum;
+            const double d = ux - (j0 - p.g) / r0;
+            acc[5] = d * d;
+        }
+        if (ux * ux > Axis<LX>::u2max || uy * uy > Axis<LY>::u2max || uz * uz > Axis<LZ>::u2max) acc[10] = 1.0;
+        if constexpr (BCY == BCY_WALL) {
+            if (y == 0) {
+                float m;
+                const float A = wall_absorbed3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z, &m);
+                acc[6] = A;
+                acc[7] = (double)m - (double)A * p.uw[0];
+            }
+            if (y == p.ny - 1) {
+                float m;
+                const float A = wall_absorbed3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z, &m);
+                acc[8] = A;
+                acc[9] = (double)m - (double)A * p.uw[1];
+            }
+        }
+    }
+    __shared__ double red[kBlock / 64][kNumStats];
+    for (int k = 0; k < kNumStats; ++k) {
+        double s = acc[k];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        acc[k] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < kNumStats; ++k) red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < kNumStats) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        p.partials[(size_t)blockIdx.x * kNumStats + threadIdx.x] = s;
+    }
+}
+
+}  // namespace glbm

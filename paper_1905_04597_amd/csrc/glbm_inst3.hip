@@ -1,0 +1,76 @@
+// Kernel instantiations of the three-dimensional lattices (glbm_device3.h):
+// -DGLBM3_COMPACT=0 padded x rows, =1 compact x rows (narrow lattices).
+// Built: D3Q27, G-D3Q125, and the channel lattices D1Q3 x G-D1Q(2N+1) x D1Q3
+// (N = 2, 3) and D1Q3 x G-D1Q(2N+2) x D1Q3 (N = 2, 3) with y periodic or
+// walls, each in the four storages.
+#include "glbm_internal.h"
+#include "glbm_device3.h"
+
+namespace glbm {
+namespace {
+
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+struct Launchers3 {
+    static hipError_t step(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t observe(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((observe3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t init(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((init3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static hipError_t stats(const KArgs &a, int grid, hipStream_t s)
+    {
+        hipLaunchKernelGGL((stats3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    static void add()
+    {
+        Variant *v = variant3_slot(LX, LY, LZ, ST, BCX, BCY);
+        v->step = &step;
+        v->observe = &observe;
+        v->init = &init;
+        v->stats = &stats;
+    }
+};
+
+template <int LX, int LY, int LZ, int BCX>
+void add_lattice3()
+{
+    Launchers3<LX, LY, LZ, ST_F32, BCX, BCY_PERIODIC>::add();
+    Launchers3<LX, LY, LZ, ST_F32S, BCX, BCY_PERIODIC>::add();
+    Launchers3<LX, LY, LZ, ST_BF16S, BCX, BCY_PERIODIC>::add();
+    Launchers3<LX, LY, LZ, ST_BF16SR, BCX, BCY_PERIODIC>::add();
+    Launchers3<LX, LY, LZ, ST_F32, BCX, BCY_WALL>::add();
+    Launchers3<LX, LY, LZ, ST_F32S, BCX, BCY_WALL>::add();
+    Launchers3<LX, LY, LZ, ST_BF16S, BCX, BCY_WALL>::add();
+    Launchers3<LX, LY, LZ, ST_BF16SR, BCX, BCY_WALL>::add();
+}
+
+}  // namespace
+
+#if GLBM3_COMPACT
+void register3_compact()
+{
+    constexpr int B = BCX_WRAP;
+#else
+void register3_padded()
+{
+    constexpr int B = BCX_PERIODIC;
+#endif
+    add_lattice3<1, 1, 1, B>();
+    add_lattice3<2, 2, 2, B>();
+    add_lattice3<1, 2, 1, B>();
+    add_lattice3<1, 3, 1, B>();
+    add_lattice3<1, kEven + 2, 1, B>();
+    add_lattice3<1, kEven + 3, 1, B>();
+}
+
+}  // namespace glbm

@@ -32,8 +32,11 @@ struct Variant {
 };
 
 // Registry of built variants, indexed by axis codes (see Axis), storage, bc_x
-// (with the row layout), bc_y.
+// (with the row layout), bc_y; three-dimensional lattices in their own.
 Variant *variant_slot(int ax, int ay, int storage, int bcx, int bcy);
+Variant *variant3_slot(int ax, int ay, int az, int storage, int bcx, int bcy);
+void register3_padded();
+void register3_compact();
 
 // One registration function per object file of glbm_inst.hip,
 // register_E_C_L(): E = 1 for the lattices with G-D1Q(2N+2) axes, C = 1 for

@@ -25,7 +25,7 @@ SYMBOLS = (
     "glbm_population_bytes", "glbm_create", "glbm_init_fields", "glbm_init_populations",
     "glbm_step", "glbm_moments", "glbm_get_populations", "glbm_stats", "glbm_info",
     "glbm_destroy", "glbm_last_error", "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy",
-    "glbm_batch_update",
+    "glbm_batch_update", "glbm_init_fields3", "glbm_moments3",
 )
 ORDER = {"member": 0, "interleave": 1, "largest_first": 2}
 
@@ -51,6 +51,9 @@ class Config(ctypes.Structure):
         ("g", ctypes.c_double),
         ("kind_x", ctypes.c_int32),
         ("kind_y", ctypes.c_int32),
+        ("nz", ctypes.c_int64),
+        ("level_z", ctypes.c_int32),
+        ("kind_z", ctypes.c_int32),
     ]
 
 
@@ -74,6 +77,7 @@ class Stats(ctypes.Structure):
         ("wall_mass", ctypes.c_double * 2),
         ("wall_momentum", ctypes.c_double * 2),
         ("nonpositive_nodes", ctypes.c_double),
+        ("momentum_z", ctypes.c_double),
     ]
 
 
@@ -97,6 +101,8 @@ def load(path: str = LIB_PATH):
     lib.glbm_init_populations.argtypes = [vp, vp]
     lib.glbm_step.argtypes = [vp, ctypes.c_int64]
     lib.glbm_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.glbm_init_fields3.argtypes = [vp, vp, vp, vp, vp]
+    lib.glbm_moments3.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.glbm_get_populations.argtypes = [vp, vp]
     lib.glbm_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.glbm_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -111,7 +117,8 @@ def load(path: str = LIB_PATH):
     lib.glbm_batch_destroy.argtypes = [vp]
     for name in ("glbm_init_fields", "glbm_init_populations", "glbm_step", "glbm_moments",
                  "glbm_get_populations", "glbm_stats", "glbm_info", "glbm_destroy",
-                 "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy", "glbm_batch_update"):
+                 "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy", "glbm_batch_update",
+                 "glbm_init_fields3", "glbm_moments3"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -124,9 +131,11 @@ def _check(rc: int, what: str):
 
 
 def make_config(dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0, bc_x="periodic", bc_y="periodic",
-                wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0, storage="f32", even_x=False, even_y=False) -> Config:
-    """even_x / even_y select the G-D1Q(2N+2) velocity set (zero velocity
-    removed) for that axis instead of G-D1Q(2N+1)."""
+                wall_u=(0.0, 0.0), end_rho=(1.0, 1.0), g=0.0, storage="f32", even_x=False, even_y=False,
+                level_z=0, nz=1, even_z=False) -> Config:
+    """even_x / even_y / even_z select the G-D1Q(2N+2) velocity set (zero
+    velocity removed) for that axis instead of G-D1Q(2N+1); dims = 3 adds a
+    periodic z axis (level_z, nz)."""
     c = Config()
     c.dims = int(dims)
     c.level_x = int(level_x)
@@ -143,6 +152,9 @@ def make_config(dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0, bc_x="per
     c.g = float(g)
     c.kind_x = AXIS_EVEN if even_x else AXIS_ODD
     c.kind_y = AXIS_EVEN if even_y else AXIS_ODD
+    c.nz = int(nz)
+    c.level_z = int(level_z)
+    c.kind_z = AXIS_EVEN if even_z else AXIS_ODD
     return c
 
 
@@ -186,12 +198,16 @@ class Solver:
         self._h = h
         self.dims = cfg.dims
         self.nx = int(cfg.nx)
-        self.ny = int(cfg.ny) if cfg.dims == 2 else 1
+        self.ny = int(cfg.ny) if cfg.dims >= 2 else 1
+        self.nz = int(cfg.nz) if cfg.dims == 3 else 1
         self.level_x = int(cfg.level_x)
-        self.level_y = int(cfg.level_y) if cfg.dims == 2 else 0
+        self.level_y = int(cfg.level_y) if cfg.dims >= 2 else 0
+        self.level_z = int(cfg.level_z) if cfg.dims == 3 else 0
         qx = 2 * self.level_x + (2 if cfg.kind_x == AXIS_EVEN else 1)
         qy = 1 if cfg.dims == 1 else 2 * self.level_y + (2 if cfg.kind_y == AXIS_EVEN else 1)
-        self.Q = qx * qy
+        qz = 1 if cfg.dims < 3 else 2 * self.level_z + (2 if cfg.kind_z == AXIS_EVEN else 1)
+        self.Q = qx * qy * qz
+        self.shape = (self.nz, self.ny, self.nx) if cfg.dims == 3 else (self.ny, self.nx)
         self._keep = []
 
     # ------------------------------------------------------------- helpers
@@ -209,15 +225,16 @@ class Solver:
         return None if t is None else ctypes.c_void_p(t.data_ptr())
 
     # ---------------------------------------------------------------- API
-    def init_fields(self, rho=None, ux=None, uy=None):
-        shp = (self.ny, self.nx)
-        r, a, b = self._dev(rho, shp), self._dev(ux, shp), self._dev(uy, shp)
+    def init_fields(self, rho=None, ux=None, uy=None, uz=None):
+        shp = self.shape
+        r, a, b, c = self._dev(rho, shp), self._dev(ux, shp), self._dev(uy, shp), self._dev(uz, shp)
         with self._torch.cuda.device(self.device):
-            _check(self.lib.glbm_init_fields(self._h, self._ptr(r), self._ptr(a), self._ptr(b)), "glbm_init_fields")
-        self._keep = [r, a, b]
+            _check(self.lib.glbm_init_fields3(self._h, self._ptr(r), self._ptr(a), self._ptr(b), self._ptr(c)),
+                   "glbm_init_fields3")
+        self._keep = [r, a, b, c]
 
     def init_populations(self, f0):
-        t = self._dev(f0, (self.Q, self.ny, self.nx))
+        t = self._dev(f0, (self.Q,) + self.shape)
         with self._torch.cuda.device(self.device):
             _check(self.lib.glbm_init_populations(self._h, self._ptr(t)), "glbm_init_populations")
         self._keep = [t]
@@ -226,17 +243,21 @@ class Solver:
         with self._torch.cuda.device(self.device):
             _check(self.lib.glbm_step(self._h, int(n)), "glbm_step")
 
-    def moments(self, which=("rho", "ux", "uy", "T", "pxy")) -> dict:
+    def moments(self, which=None) -> dict:
+        """rho, ux, uy, T, pxy (and uz in three dimensions) of f(t), shaped
+        like the lattice ([nz][ny][nx] or [ny][nx])."""
         torch = self._torch
-        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) for k in which}
-        ptrs = [self._ptr(out.get(k)) for k in ("rho", "ux", "uy", "T", "pxy")]
+        if which is None:
+            which = ("rho", "ux", "uy", "uz", "T", "pxy") if self.dims == 3 else ("rho", "ux", "uy", "T", "pxy")
+        out = {k: torch.empty(self.shape, dtype=torch.float32, device=self.device) for k in which}
+        ptrs = [self._ptr(out.get(k)) for k in ("rho", "ux", "uy", "uz", "T", "pxy")]
         with torch.cuda.device(self.device):
-            _check(self.lib.glbm_moments(self._h, *ptrs), "glbm_moments")
+            _check(self.lib.glbm_moments3(self._h, *ptrs), "glbm_moments3")
         return out
 
     def populations(self):
         torch = self._torch
-        out = torch.empty((self.Q, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        out = torch.empty((self.Q,) + self.shape, dtype=torch.float32, device=self.device)
         with torch.cuda.device(self.device):
             _check(self.lib.glbm_get_populations(self._h, self._ptr(out)), "glbm_get_populations")
         return out
@@ -250,7 +271,7 @@ class Solver:
             "energy_post": s.energy_post, "residual": s.residual,
             "wall_mass_bottom": s.wall_mass[0], "wall_mass_top": s.wall_mass[1],
             "wall_momentum_bottom": s.wall_momentum[0], "wall_momentum_top": s.wall_momentum[1],
-            "nonpositive_nodes": s.nonpositive_nodes,
+            "nonpositive_nodes": s.nonpositive_nodes, "momentum_z": s.momentum_z,
         }
 
     def info(self) -> dict:

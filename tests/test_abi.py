@@ -65,7 +65,7 @@ def test_population_bytes_layout():
 
 
 @pytest.mark.parametrize("kwargs,needle", [
-    (dict(dims=3, level_x=1), "dims"),
+    (dict(dims=4, level_x=1), "dims"),
     (dict(dims=1, level_x=0, nx=10), "level_x"),
     (dict(dims=1, level_x=8, nx=10), "level_x"),
     (dict(dims=2, level_x=3, level_y=3, nx=4, ny=5, bc_y="wall"), "fastest y velocity"),
@@ -79,6 +79,22 @@ def test_invalid_configs_are_rejected(kwargs, needle):
     c = glbm.make_config(**kwargs)
     assert glbm.load().glbm_population_bytes(ctypes.byref(c)) == 0
     assert needle in glbm.load().glbm_last_error().decode()
+
+
+def test_three_dimensional_layout_and_checks():
+    # [q][z][y][row], each plane rounded to 256 bytes; D3Q27, padded rows
+    c = glbm.make_config(3, 1, 1, 70, 9, tau=0.7, level_z=1, nz=6, storage="f32")
+    assert glbm.population_bytes(c) == 27 * ((6 * 9 * 192 * 4 + 255) // 256 * 256)
+    # compact rows for nx < 64
+    c = glbm.make_config(3, 1, 3, 4, 20, kn=0.1, bc_y="wall", level_z=1, nz=5, storage="f32_shifted")
+    assert glbm.population_bytes(c) == 63 * ((5 * 20 * 4 * 4 + 255) // 256 * 256)
+    lib = glbm.load()
+    bad = glbm.make_config(3, 1, 1, 8, 4, tau=0.8, level_z=3, nz=2)
+    assert lib.glbm_population_bytes(ctypes.byref(bad)) == 0
+    assert "fastest z velocity" in lib.glbm_last_error().decode()
+    bad = glbm.make_config(3, 1, 1, 8, 4, tau=0.8, level_z=1, nz=4, bc_x="eq_ends")
+    assert lib.glbm_population_bytes(ctypes.byref(bad)) == 0
+    assert "periodic in x" in lib.glbm_last_error().decode()
 
 
 def test_axis_kind_is_validated():

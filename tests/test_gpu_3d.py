@@ -1,0 +1,120 @@
+"""Three-dimensional lattices on the GPU against the FP64 oracle
+(tensor product of three axes, periodic in x and z, y periodic or walls).
+
+Cases span several tiles with ragged tails, both row layouts (compact rows
+for nx < 64), odd and even wall-normal axes, force, moving walls, and the
+four storages on one channel case; FP32 deviation storage is held to 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04597_amd import glbm
+from tests.gpu_common import BOUND, compare_moments, fmt, rel_err
+
+pytestmark = pytest.mark.gpu
+
+F32 = ("f32", "f32_shifted")
+
+CASES = {
+    # name: (levels (x, y, z), even_y, nx, ny, nz, extra, init, steps, storages)
+    "d3q27_periodic_fields": ((1, 1, 1), False, 70, 9, 6, dict(tau=0.7, g=1e-4), "fields", 10, F32),
+    "d3q27_walls_compact": ((1, 1, 1), False, 5, 12, 7, dict(kn=0.2, bc_y="wall", wall_u=(-0.05, 0.05)),
+                            "fields", 20, ("f32", "f32_shifted", "bf16_shifted_sr")),
+    "g_d3q125_periodic_pops": ((2, 2, 2), False, 66, 5, 4, dict(tau=0.9, g=2e-4), "populations", 8, F32),
+    "g_d3q125_walls_fields": ((2, 2, 2), False, 9, 10, 3, dict(tau=1.1, bc_y="wall", wall_u=(0.03, -0.02)),
+                              "fields", 10, F32),
+    "d1q3xd1q7xd1q3_channel": ((1, 3, 1), False, 4, 20, 5, dict(kn=0.1, bc_y="wall", wall_u=(-0.04, 0.04), g=2e-5),
+                               "rest", 200, ("f32", "f32_shifted", "bf16_shifted_sr")),
+    "d1q3xd1q8xd1q3_channel": ((1, 3, 1), True, 67, 16, 3, dict(kn=0.3, bc_y="wall", wall_u=(0.0, 0.05), g=1e-5),
+                               "fields", 30, F32),
+    "d1q3xd1q6xd1q3_periodic": ((1, 2, 1), True, 8, 6, 9, dict(tau=0.8, g=1e-4), "populations", 12, F32),
+}
+PARAMS = [(n, st) for n, c in CASES.items() for st in c[-1]]
+
+
+def _pair(case, storage):
+    (lx, ly, lz), ey, nx, ny, nz, extra, _, _, _ = case
+    bcy = extra.get("bc_y", "periodic")
+    orc = oracle.OracleSolver(3, lx, ly, nx, ny, tau=extra.get("tau", 0.0), kn=extra.get("kn", 0.0),
+                              bc_y=oracle.BC_WALL if bcy == "wall" else oracle.BC_PERIODIC,
+                              wall_u=extra.get("wall_u", (0, 0)), g=extra.get("g", 0.0), even_y=ey,
+                              level_z=lz, nz=nz)
+    cfg = glbm.make_config(3, lx, ly, nx, ny, tau=extra.get("tau", 0.0), kn=extra.get("kn", 0.0), bc_y=bcy,
+                           wall_u=extra.get("wall_u", (0, 0)), g=extra.get("g", 0.0), storage=storage, even_y=ey,
+                           level_z=lz, nz=nz)
+    return orc, glbm.Solver(cfg)
+
+
+def _moments(gpu):
+    import torch
+
+    m = gpu.moments()
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in m.items()}
+
+
+@pytest.mark.parametrize("name,storage", PARAMS, ids=["%s-%s" % p for p in PARAMS])
+def test_3d_parity_with_oracle(name, storage):
+    case = CASES[name]
+    (lx, ly, lz), ey, nx, ny, nz, extra, init, steps, _ = case
+    print("\n[3d] case=%s storage=%s steps=%d" % (name, storage, steps), flush=True)
+    orc, gpu = _pair(case, storage)
+    if init == "rest":
+        orc.init_fields()
+        gpu.init_fields()
+    elif init == "fields":
+        rng = np.random.default_rng(31)
+        f = [(1.0 + 0.05 * rng.uniform(-1, 1, (nz, ny, nx))).astype(np.float32)]
+        f += [(0.05 * rng.uniform(-1, 1, (nz, ny, nx))).astype(np.float32) for _ in range(3)]
+        orc.init_fields(*[a.astype(np.float64) for a in f])
+        gpu.init_fields(*f)
+    else:
+        rng = np.random.default_rng(32)
+        f0 = ((1.0 + 0.5 * rng.uniform(-1, 1, (orc.Q, nz, ny, nx))) / orc.Q).astype(np.float32)
+        orc.init_populations(f0.astype(np.float64))
+        gpu.init_populations(f0)
+    orc.step(steps)
+    gpu.step(steps)
+    th = max((4 * ly + 3) / 3.0 if ey else ly / 3.0, lx / 3.0, lz / 3.0)
+    ref, got = orc.moments(), _moments(gpu)
+    errs = compare_moments(ref, got, th)
+    du = float(np.max(np.abs(got["uz"] - ref["uz"]))) / max(float(np.max(np.abs(ref["uz"]))), 1e-2)
+    fe = rel_err(gpu.populations().cpu().numpy(), orc.populations())
+    print("[3d] t=%d %s uz %.2e populations %.2e" % (steps, fmt(errs), du, fe), flush=True)
+    tol = BOUND[storage]
+    assert max(errs.values()) <= tol and du <= tol and fe <= tol
+    so, sg = orc.stats(), gpu.stats()
+    assert abs(sg["mass"] - so["mass"]) <= tol * abs(so["mass"])
+    for k in ("momentum_x", "momentum_y", "momentum_z"):
+        assert abs(sg[k] - so[k]) <= tol * max(abs(so[k]), 1e-2 * orc.nodes), k
+    if extra.get("bc_y") == "wall":
+        for k in ("wall_mass_bottom", "wall_mass_top"):
+            assert sg[k] == pytest.approx(so[k], rel=tol)
+        for k in ("wall_momentum_bottom", "wall_momentum_top"):
+            assert abs(sg[k] - so[k]) <= tol * max(abs(so[k]), 1e-2 * nx * nz)
+
+
+def test_3d_free_streaming_permutation_bitwise():
+    nx, ny, nz = 70, 5, 4
+    cfg = glbm.make_config(3, 1, 2, nx, ny, tau=1e30, level_z=1, nz=nz)
+    gpu = glbm.Solver(cfg)
+    Q = 3 * 5 * 3
+    rng = np.random.default_rng(4)
+    f0 = ((1.0 + 0.5 * rng.uniform(-1, 1, (Q, nz, ny, nx))) / Q).astype(np.float32)
+    gpu.init_populations(f0)
+    period = math.lcm(nx, ny, nz)
+    gpu.step(period - 1)
+    assert not np.array_equal(gpu.populations().cpu().numpy(), f0)
+    gpu.step(1)
+    assert np.array_equal(gpu.populations().cpu().numpy(), f0)
+
+
+def test_3d_members_are_refused_by_batches():
+    cfg = glbm.make_config(3, 1, 1, 8, 4, tau=0.8, level_z=1, nz=4)
+    s = glbm.Solver(cfg)
+    s.init_fields()
+    with pytest.raises(glbm.GlbmError, match="one- and two-dimensional"):
+        glbm.Batch([s])
