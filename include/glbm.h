@@ -127,10 +127,10 @@ typedef struct glbm_stats {
 typedef struct glbm_solver glbm_t;
 
 /* Bytes of ONE population buffer for cfg (the library's internal layout:
- * velocity planes [q][y][row], each plane rounded up to 256 bytes; a row is
- * nx columns plus ghost columns padded to a multiple of 64, or exactly nx
- * columns for two-dimensional lattices with periodic x and nx < 64), or 0 if
- * cfg is invalid.  The caller
+ * velocity planes [q][row][column], each plane rounded up to 256 bytes; two-
+ * and three-dimensional lattices have compact rows of exactly nx columns
+ * (rows y, or z * ny + y), one-dimensional ones one row of nx columns plus
+ * ghost columns padded to a multiple of 64), or 0 if cfg is invalid.  The caller
  * allocates two such buffers on the device (for HBM-budget admission this is
  * the whole device footprint apart from a few KB of tables). */
 size_t glbm_population_bytes(const glbm_config *cfg);

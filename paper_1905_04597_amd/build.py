@@ -63,12 +63,13 @@ def _compile(args):
 def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     # the three-dimensional objects are among the slowest: start them first
-    tasks = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3%s.o" % ("c" if c else "")),
-              ["-DGLBM3_COMPACT=%d" % c]) for c in (0, 1)]
+    tasks = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3.o"), [])]
     tasks.append((os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), []))
     for lv in LEVELS:
         for even in (0, 1):
             for compact in (0, 1):
+                if lv == 0 and not compact:
+                    continue  # the mixed lattices are two-dimensional only
                 tasks.append((os.path.join(CSRC, "glbm_inst.hip"),
                               os.path.join(BUILD, "glbm_inst_%s%d%s.o" % ("e" if even else "", lv,
                                                                          "c" if compact else "")),

@@ -48,8 +48,7 @@ void register_all()
 #define GLBM_CALL_REGISTER(E, C, L) register_##E##_##C##_##L();
     GLBM_OBJECTS(GLBM_CALL_REGISTER)
 #undef GLBM_CALL_REGISTER
-    register3_padded();
-    register3_compact();
+    register3();
 }
 
 // Host copy of the per-axis equilibrium at rho = 1 (N-fold convolution of the
@@ -162,9 +161,10 @@ int check_config(const glbm_config *c, Geometry *g)
     g->nx = nx;
     g->ny = ny;
     g->nz = nz;
-    // periodic x narrower than a wave: compact rows of nx columns (node x at
-    // column x); otherwise padded rows with ghosts (node x at column kGhost + x)
-    const bool compact = c->dims >= 2 && c->bc_x == GLBM_BC_PERIODIC && nx < kCompactBelow;
+    // two and three dimensions (periodic x): compact rows of nx columns (node
+    // x at column x, the x wrap taken per lane in the pull); one dimension:
+    // padded rows with ghosts (node x at column kGhost + x)
+    const bool compact = c->dims >= 2 && c->bc_x == GLBM_BC_PERIODIC;
     g->bcx = compact ? BCX_WRAP : c->bc_x == GLBM_BC_EQ_ENDS ? BCX_EQ : BCX_PERIODIC;
     g->nxp = compact ? nx : (kGhost + nx + ax.vmax + 63) / 64 * 64;
     g->plane_bytes = ((uint64_t)(nz * ny * g->nxp) * g->eb + 255) & ~(uint64_t)255;

@@ -8,20 +8,24 @@
 //   (section 4) -> BGK relaxation with collision frequency 1/(tau + 1/2)
 //   plus the linear force of section 5.4 -> store.
 //
-// Memory layout of a population buffer: velocity planes [q][y][xp] with rows
-// of nxp padded columns (a multiple of 64); node x lives at column x + G,
-// G = 64, so that a wave of 64 nodes reads and writes whole, aligned cache
-// lines of its own row.  The columns within reach of the fastest x velocity
-// on each side of the interior are ghosts.  With periodic x every store of an edge node is replicated into the
-// matching ghost columns, so a pull never wraps: the source of velocity c_x
-// sits at a constant byte shift from the node, which the buffer loads take as
-// an immediate offset.  With fixed equilibrium ends the ghosts hold the end
-// state and are never written.
+// Memory layout of a population buffer: velocity planes [q][row][column].
 //
-// Narrow periodic lattices (nx below one wave) use a compact layout instead:
-// rows of exactly nx columns and no ghosts, so that a wave's 64 nodes are 64
-// consecutive values of each plane (several whole rows); the pull computes
-// the source column (x - c_x) mod nx once per velocity.
+// Two- and three-dimensional lattices (periodic x) use compact rows of
+// exactly nx columns (rows y, or z * ny + y): each plane is one contiguous
+// run of nodes, so that consecutive workgroups stream consecutive bytes of
+// every plane whatever nx is.  The pull computes the source column
+// (x - c_x) mod nx once per x velocity, a per-lane register; the y and z
+// shifts are whole rows.  (Padded rows with ghost columns measured slower
+// here: the ghosts and the row padding break the planes into short runs.)
+//
+// One-dimensional lattices use one padded row of nxp columns (a multiple of
+// 64); node x lives at column x + G, G = 64.  The columns within reach of the
+// fastest x velocity on each side of the interior are ghosts.  With periodic
+// x every store of an edge node is replicated into the matching ghost
+// columns, so a pull never wraps: the source of velocity c_x sits at a
+// constant byte shift from the node, which the buffer loads take as an
+// immediate offset.  With fixed equilibrium ends the ghosts hold the end
+// state and are never written.
 //
 // Tables that depend only on the level (rest weights, half flux, force
 // shape) are compile-time constants folded into the instructions; tables
@@ -41,12 +45,12 @@ constexpr int kMaxQ1 = 2 * kMaxLevel + 2;  // velocities of the largest axis
 constexpr int kBlock = 256;
 constexpr int kNumStats = 12;
 constexpr int kGhost = 64;  // padded column of node x = 0 (>= the largest level)
-constexpr int kCompactBelow = 64;  // periodic-x lattices narrower than this use compact rows
 
 enum StorageKind { ST_F32 = 0, ST_F32S = 1, ST_BF16S = 2, ST_BF16SR = 3 };
-// x boundary and row layout: periodic x with ghost columns (padded rows),
-// periodic x in the compact layout of narrow lattices (rows of exactly nx
-// columns, the pull wraps), fixed equilibrium ends (ghosts hold the ends).
+// x boundary and row layout: periodic x with ghost columns (padded rows, one
+// dimension), periodic x in compact rows (rows of exactly nx columns, the
+// pull wraps; two and three dimensions), fixed equilibrium ends (padded rows
+// whose ghosts hold the ends).
 enum BcX { BCX_PERIODIC = 0, BCX_WRAP = 1, BCX_EQ = 2 };
 enum BcY { BCY_PERIODIC = 0, BCY_WALL = 1 };
 

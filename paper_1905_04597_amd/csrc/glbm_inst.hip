@@ -1,9 +1,10 @@
 // Kernel instantiations for one hierarchy level, selected at compile time
 // with -DGLBM_LEVEL=N (N = 1..7); -DGLBM_LEVEL=0 builds the mixed lattices.
 // -DGLBM_EVEN=1 builds the lattices of G-D1Q(2N+2) axes instead of
-// G-D1Q(2N+1) ones; -DGLBM_COMPACT=1 the compact-row variants of the 2D
-// periodic-x lattices (narrow lattices).  Each (axis kind, layout, level) is
-// its own object file so the build runs in parallel.
+// G-D1Q(2N+1) ones.  -DGLBM_COMPACT=0 builds the one-dimensional lattices
+// (padded rows), -DGLBM_COMPACT=1 the two-dimensional ones (periodic x in
+// compact rows).  Each (axis kind, dimension, level) is its own object file
+// so the build runs in parallel.
 #include "glbm_internal.h"
 
 namespace glbm {
@@ -111,34 +112,27 @@ void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, GLBM_LEVEL)()
 {
     constexpr int N = GLBM_LEVEL, A = GLBM_AX(GLBM_LEVEL);
 #if GLBM_COMPACT
-    // two dimensions, periodic x in compact rows (narrow lattices)
+    // two dimensions, the same axis twice, periodic x in compact rows:
+    // periodic or walls across y (the symmetric even lattices up to N = 6:
+    // (2N+2)^2 <= 196 velocities)
     if constexpr (!GLBM_EVEN || N <= 6) {
         add_all_storages<A, A, BCX_WRAP, BCY_PERIODIC>();
         add_all_storages<A, A, BCX_WRAP, BCY_WALL>();
     }
 #else
-    // one dimension: periodic or fixed equilibrium ends
+    // one dimension: periodic or fixed equilibrium ends (padded rows)
     add_all_storages<A, 0, BCX_PERIODIC, BCY_PERIODIC>();
     add_all_storages<A, 0, BCX_EQ, BCY_PERIODIC>();
-    // two dimensions, the same axis twice: periodic or walls across y (the
-    // symmetric even lattices up to N = 6: (2N+2)^2 <= 196 velocities)
-    if constexpr (!GLBM_EVEN || N <= 6) {
-        add_all_storages<A, A, BCX_PERIODIC, BCY_PERIODIC>();
-        add_all_storages<A, A, BCX_PERIODIC, BCY_WALL>();
-    }
 #endif
     (void)N;
 }
-#else
+#elif GLBM_COMPACT
 // Mixed lattices D1Q3 (streamwise x) x G-D1Q(2N+1) or G-D1Q(2N+2) (across the
-// walls), the form the channel flows of sections 5.3-5.4 use.
+// walls), the form the channel flows of sections 5.3-5.4 use; periodic x in
+// compact rows.
 void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, 0)()
 {
-#if GLBM_COMPACT
     constexpr int BX = BCX_WRAP;
-#else
-    constexpr int BX = BCX_PERIODIC;
-#endif
 #if !GLBM_EVEN
     add_all_storages<1, 2, BX, BCY_WALL>();
 #else
@@ -151,6 +145,8 @@ void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, 0)()
     add_all_storages<1, GLBM_AX(6), BX, BCY_WALL>();
     add_all_storages<1, GLBM_AX(7), BX, BCY_WALL>();
 }
+#else
+#error "the mixed lattices are two-dimensional: build them with -DGLBM_COMPACT=1"
 #endif
 
 }  // namespace glbm

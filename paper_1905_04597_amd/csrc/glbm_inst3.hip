@@ -1,6 +1,5 @@
-// Kernel instantiations of the three-dimensional lattices (glbm_device3.h):
-// -DGLBM3_COMPACT=0 padded x rows, =1 compact x rows (narrow lattices).
-// Built: D3Q27, G-D3Q125, and the channel lattices D1Q3 x G-D1Q(2N+1) x D1Q3
+// Kernel instantiations of the three-dimensional lattices (glbm_device3.h),
+// periodic x in compact rows.  Built: D3Q27, G-D3Q125, and the channel lattices D1Q3 x G-D1Q(2N+1) x D1Q3
 // (N = 2, 3) and D1Q3 x G-D1Q(2N+2) x D1Q3 (N = 2, 3) with y periodic or
 // walls, each in the four storages.
 #include "glbm_internal.h"
@@ -41,9 +40,10 @@ struct Launchers3 {
     }
 };
 
-template <int LX, int LY, int LZ, int BCX>
+template <int LX, int LY, int LZ>
 void add_lattice3()
 {
+    constexpr int BCX = BCX_WRAP;
     Launchers3<LX, LY, LZ, ST_F32, BCX, BCY_PERIODIC>::add();
     Launchers3<LX, LY, LZ, ST_F32S, BCX, BCY_PERIODIC>::add();
     Launchers3<LX, LY, LZ, ST_BF16S, BCX, BCY_PERIODIC>::add();
@@ -56,21 +56,14 @@ void add_lattice3()
 
 }  // namespace
 
-#if GLBM3_COMPACT
-void register3_compact()
+void register3()
 {
-    constexpr int B = BCX_WRAP;
-#else
-void register3_padded()
-{
-    constexpr int B = BCX_PERIODIC;
-#endif
-    add_lattice3<1, 1, 1, B>();
-    add_lattice3<2, 2, 2, B>();
-    add_lattice3<1, 2, 1, B>();
-    add_lattice3<1, 3, 1, B>();
-    add_lattice3<1, kEven + 2, 1, B>();
-    add_lattice3<1, kEven + 3, 1, B>();
+    add_lattice3<1, 1, 1>();
+    add_lattice3<2, 2, 2>();
+    add_lattice3<1, 2, 1>();
+    add_lattice3<1, 3, 1>();
+    add_lattice3<1, kEven + 2, 1>();
+    add_lattice3<1, kEven + 3, 1>();
 }
 
 }  // namespace glbm

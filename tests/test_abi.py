@@ -39,24 +39,26 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_population_bytes_layout():
-    # [q][y][nxp], nxp = 64 + nx + N rounded up to a multiple of 64 columns,
-    # times the element size of the storage, each plane rounded to 256 bytes
+    # one dimension: one padded row of nxp = 64 + nx + N columns rounded up to
+    # a multiple of 64, times the element size, each plane rounded to 256 bytes
     def nxp(nx, N):
         return (64 + nx + N + 63) // 64 * 64
-    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="f32")
-    assert glbm.population_bytes(c) == ((121 * 1024 * nxp(4096, 5) * 4 + 255) // 256) * 256
-    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="bf16_shifted")
-    assert glbm.population_bytes(c) == ((121 * 1024 * nxp(4096, 5) * 2 + 255) // 256) * 256
     c = glbm.make_config(1, 3, 0, 2000, 1, kn=0.01, bc_x="eq_ends")
     assert glbm.population_bytes(c) == ((7 * nxp(2000, 3) * 4 + 255) // 256) * 256
-    # two dimensions, periodic x narrower than 64: compact rows of nx columns,
-    # each plane rounded up to 256 bytes
+    c = glbm.make_config(1, 4, 0, 1000, 1, tau=0.7, storage="bf16_shifted")
+    assert glbm.population_bytes(c) == 9 * ((nxp(1000, 4) * 2 + 255) // 256 * 256)
+    # two dimensions: compact rows of nx columns, each plane rounded up to 256
+    # bytes, whatever nx
+    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="f32")
+    assert glbm.population_bytes(c) == 121 * 1024 * 4096 * 4
+    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="bf16_shifted")
+    assert glbm.population_bytes(c) == 121 * 1024 * 4096 * 2
     c = glbm.make_config(2, 3, 3, 4, 37, kn=0.1, bc_y="wall", storage="f32_shifted")
     assert glbm.population_bytes(c) == 49 * ((37 * 4 * 4 + 255) // 256 * 256)
     c = glbm.make_config(2, 6, 6, 63, 100, tau=0.8, storage="bf16_shifted_sr")
     assert glbm.population_bytes(c) == 169 * ((100 * 63 * 2 + 255) // 256 * 256)
-    c = glbm.make_config(2, 6, 6, 64, 100, tau=0.8, storage="bf16_shifted_sr")
-    assert glbm.population_bytes(c) == 169 * 100 * nxp(64, 6) * 2
+    c = glbm.make_config(2, 6, 6, 70, 33, tau=0.8, storage="bf16_shifted_sr")
+    assert glbm.population_bytes(c) == 169 * ((33 * 70 * 2 + 255) // 256 * 256)
     # G-D1Q(2N+2) axes: 2N+2 velocities, ghosts as deep as the fastest one (2N+1)
     c = glbm.make_config(1, 3, 0, 500, 1, kn=0.01, bc_x="eq_ends", even_x=True)
     assert glbm.population_bytes(c) == 8 * nxp(500, 7) * 4
@@ -82,10 +84,9 @@ def test_invalid_configs_are_rejected(kwargs, needle):
 
 
 def test_three_dimensional_layout_and_checks():
-    # [q][z][y][row], each plane rounded to 256 bytes; D3Q27, padded rows
+    # [q][z][y][x], compact rows, each plane rounded to 256 bytes
     c = glbm.make_config(3, 1, 1, 70, 9, tau=0.7, level_z=1, nz=6, storage="f32")
-    assert glbm.population_bytes(c) == 27 * ((6 * 9 * 192 * 4 + 255) // 256 * 256)
-    # compact rows for nx < 64
+    assert glbm.population_bytes(c) == 27 * ((6 * 9 * 70 * 4 + 255) // 256 * 256)
     c = glbm.make_config(3, 1, 3, 4, 20, kn=0.1, bc_y="wall", level_z=1, nz=5, storage="f32_shifted")
     assert glbm.population_bytes(c) == 63 * ((5 * 20 * 4 * 4 + 255) // 256 * 256)
     lib = glbm.load()

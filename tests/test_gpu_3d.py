@@ -1,9 +1,10 @@
 """Three-dimensional lattices on the GPU against the FP64 oracle
 (tensor product of three axes, periodic in x and z, y periodic or walls).
 
-Cases span several tiles with ragged tails, both row layouts (compact rows
-for nx < 64), odd and even wall-normal axes, force, moving walls, and the
-four storages on one channel case; FP32 deviation storage is held to 1e-5.
+Cases span several tiles with ragged tails, narrow x (the pull wrapping the
+row) and wider x, odd and even wall-normal axes, force, moving walls, and
+the four storages on one channel case; FP32 deviation storage is held to
+1e-5.
 """
 import math
 
@@ -21,7 +22,7 @@ F32 = ("f32", "f32_shifted")
 CASES = {
     # name: (levels (x, y, z), even_y, nx, ny, nz, extra, init, steps, storages)
     "d3q27_periodic_fields": ((1, 1, 1), False, 70, 9, 6, dict(tau=0.7, g=1e-4), "fields", 10, F32),
-    "d3q27_walls_compact": ((1, 1, 1), False, 5, 12, 7, dict(kn=0.2, bc_y="wall", wall_u=(-0.05, 0.05)),
+    "d3q27_walls_narrow": ((1, 1, 1), False, 5, 12, 7, dict(kn=0.2, bc_y="wall", wall_u=(-0.05, 0.05)),
                             "fields", 20, ("f32", "f32_shifted", "bf16_shifted_sr")),
     "g_d3q125_periodic_pops": ((2, 2, 2), False, 66, 5, 4, dict(tau=0.9, g=2e-4), "populations", 8, F32),
     "g_d3q125_walls_fields": ((2, 2, 2), False, 9, 10, 3, dict(tau=1.1, bc_y="wall", wall_u=(0.03, -0.02)),

@@ -6,9 +6,10 @@ relative error max|q - q_ref| / max|q_ref| (floors in tests/gpu_common.py):
 1e-5 for FP32 storage, 1e-3 for BF16 storage.  Sizes span several 256-node
 tiles with a ragged tail, plus the degenerate shapes (nx below the level, so
 that ghost columns or the pull wrap several times; nx = 3 or 4 channels;
-1D).  Two-dimensional lattices with periodic x and nx < 64 run in compact
-rows (no ghosts, the pull wraps), the others in padded rows: both layouts
-are covered, and x-uniform channels are compared bitwise across them.
+1D).  Two-dimensional lattices run in compact rows (no ghosts, the pull
+wraps per lane), one-dimensional ones in padded rows with ghost columns:
+both layouts are covered, and x-uniform channels are compared bitwise
+between a narrow width (the pull wrapping more than once) and a wide one.
 
 Which storage meets which bound (tests/gpu_common.py BOUND): FP32 deviation
 storage (f - S, the FP32 path) meets 1e-5 on every case.  Plain FP32 keeps
@@ -126,7 +127,7 @@ def test_parity_with_oracle(name, storage):
     assert sg["nonpositive_nodes"] == so["nonpositive_nodes"]
 
 
-@pytest.mark.parametrize("nx,ny", [(5, 6), (66, 6)], ids=["compact_rows", "padded_rows"])
+@pytest.mark.parametrize("nx,ny", [(5, 6), (66, 6)], ids=["narrow", "wide"])
 def test_free_streaming_permutation_bitwise(nx, ny):
     """tau = 1e30 gives omega = 1e-30: the relaxation term rounds away and a
     step is a pure permutation, so the state returns bitwise after lcm(nx, ny)."""
@@ -145,11 +146,11 @@ def test_free_streaming_permutation_bitwise(nx, ny):
 
 @pytest.mark.parametrize("storage", ["f32_shifted", "f32"])
 @pytest.mark.parametrize("level", [2, 5])
-def test_compact_rows_match_padded_rows_bitwise(level, storage):
+def test_narrow_channel_matches_wide_channel_bitwise(level, storage):
     """An x-uniform channel (fields varying across y only) evolves the same in
     every column whatever the width, and a node's arithmetic does not depend
-    on the row layout: the columns of a 4-wide lattice (compact rows) equal
-    those of a 64-wide one (padded rows) bitwise."""
+    on where its x sources sit: the columns of a 4-wide lattice (each x pull
+    wrapping the row up to twice) equal those of a 64-wide one bitwise."""
     from paper_1905_04597_amd import glbm
 
     ny = 40
