@@ -91,7 +91,7 @@ def sod_density(nodes: int, rho_left: float, rho_right: float) -> np.ndarray:
 
 def random_fields(seed: int, nx: int, ny: int, rho_amp: float = 0.05, u_amp: float = 0.05,
                   dims: int = 2):
-    """Smooth-free random density/velocity fields (float32), rho around 1."""
+    """Smooth-free random density/velocity fields (float32), rho near 1."""
     rng = np.random.default_rng(seed)
     rho = (1.0 + rho_amp * rng.uniform(-1, 1, size=(ny, nx))).astype(np.float32)
     ux = (u_amp * rng.uniform(-1, 1, size=(ny, nx))).astype(np.float32)

@@ -1,6 +1,5 @@
 """Pins of the oracle in three dimensions: the tensor product of three axes
-(section 4 extended to a third axis, SURVEY's N4), periodic in z, walls
-across y.
+(section 4 extended to a third axis), periodic in z, walls across y.
 
 * the time stepper against the push-form brute-force stepper (3D);
 * conservation of mass and momentum, the force adding g per node and step,
