@@ -6,7 +6,10 @@
 * a uniform equilibrium is a fixed point;
 * free-molecular Couette flow (omega = 0) reaches a closed-form state;
 * a small shear wave decays at the rate nu k^2 with nu = theta tau
-  (sections 5.1/5.2: nu = theta tau for the collision frequency 1/(tau + 1/2)).
+  (sections 5.1/5.2: nu = theta tau for the collision frequency 1/(tau + 1/2));
+* the same wave follows, step by step, the linearised one-step operator of
+  the scheme in Fourier space, built here from the D1Q3 factor and its
+  derivative (matrix powers and the eigenvalue of the shear mode).
 """
 import math
 
@@ -172,6 +175,75 @@ def test_shear_wave_decay_rate(N):
     rate = -math.log(a1 / a0) / 400
     nu = (N / 3.0) * tau
     assert rate == pytest.approx(nu * k * k, rel=0.02)
+
+
+def _axis_linear(N, even):
+    """Velocities, rest weights and du-derivative at u = 0 of one axis
+    equilibrium.  Odd axis: the N-fold convolution of D1Q3 at u/N (section 2);
+    each factor (1/6, 2/3, 1/6) has derivative (-1/2, 0, 1/2)/N, so the
+    derivative of the product is (-1/2, 0, 1/2) convolved with N-1 factors.
+    Even axis (2N+2 velocities on the half grid): the 2N+1 equilibrium at u/2,
+    each velocity taking half of each neighbour."""
+    d1q3, dd = np.array([1 / 6, 2 / 3, 1 / 6]), np.array([-0.5, 0.0, 0.5])
+    W = np.array([1.0])
+    for _ in range(N - 1):
+        W = np.convolve(W, d1q3)
+    Wd, W = np.convolve(dd, W), np.convolve(d1q3, W)
+    if not even:
+        return np.arange(-N, N + 1), W, Wd
+    Wd = Wd / 2  # d/du of F(u/2)
+    pad = lambda a: np.concatenate([[0.0], a, [0.0]])
+    avg = lambda a: (pad(a)[:-1] + pad(a)[1:]) / 2
+    return np.arange(-(2 * N + 1), 2 * N + 2, 2), avg(W), avg(Wd)
+
+
+def _linear_operator(Nx, Ny, even_y, k, omega):
+    """One step of the scheme linearised about rest (rho = 1, u = 0) for a
+    perturbation ~ exp(i k y): relax toward the linearised product
+    equilibrium, then pull-stream (multiply by exp(-i k c_y))."""
+    cx, Wx, Wdx = _axis_linear(Nx, False)
+    cy, Wy, Wdy = _axis_linear(Ny, even_y)
+    CX = np.repeat(cx[None, :], len(cy), 0).ravel()
+    CY = np.repeat(cy[:, None], len(cx), 1).ravel()
+    W = np.outer(Wy, Wx).ravel()
+    Gx = np.outer(Wy, Wdx).ravel()  # d f^eq / d u_x
+    Gy = np.outer(Wdy, Wx).ravel()  # d f^eq / d u_y
+    J = np.outer(W, np.ones_like(W)) + np.outer(Gx, CX) + np.outer(Gy, CY)
+    C = (1 - omega) * np.eye(len(W)) + omega * J
+    return np.exp(-1j * k * CY)[:, None] * C, Gx, CX
+
+
+@pytest.mark.parametrize("Nx,Ny,even_y", [(1, 1, False), (2, 2, False), (3, 3, False), (1, 2, True), (1, 3, True)])
+def test_shear_wave_follows_the_linearised_operator(Nx, Ny, even_y):
+    """u_x = A sin(k y) (A = 1e-7, nonlinear terms ~ A^2) on a periodic
+    lattice: the projection a(t) = sum_y u_x sin(k y) equals
+    A (ny/2) Re(c_x^T M^t v0) of the linearised operator M exactly (to the
+    size of the neglected terms) at every t, and late-time ratios
+    a(t+1)/a(t) tend to the shear-mode eigenvalue of M."""
+    ny, tau, A = 64, 0.7, 1e-7
+    s = oracle.OracleSolver(2, Nx, Ny, 1, ny, tau=tau, even_y=even_y)
+    k = 2 * math.pi / ny
+    y = np.arange(ny)
+    s.init_fields(np.ones(ny), A * np.sin(k * y), np.zeros(ny))
+    M, v0, CX = _linear_operator(Nx, Ny, even_y, k, 1.0 / (tau + 0.5))
+    assert float(CX @ v0) == pytest.approx(1.0, abs=1e-14)  # first moment of the derivative is 1
+    v, t = v0.astype(complex), 0
+    for target in (1, 5, 30, 120, 121):
+        while t < target:
+            v = M @ v
+            t += 1
+        s.step(target - s.time)
+        a = float((s.moments()["ux"][:, 0] * np.sin(k * y)).sum())
+        pred = A * ny / 2 * float((CX @ v).real)
+        assert a == pytest.approx(pred, rel=1e-7, abs=1e-12 * A), (t, a, pred)
+        if target == 120:
+            a120 = a
+    lam = np.linalg.eigvals(M)
+    # the shear mode: the eigenvalue nearest exp(-nu k^2) with nu = theta_y tau
+    theta_y = (4 * Ny + 3) / 3.0 if even_y else Ny / 3.0
+    shear = lam[np.argmin(np.abs(lam - math.exp(-theta_y * tau * k * k)))]
+    assert abs(shear.imag) < 1e-12
+    assert a / a120 == pytest.approx(shear.real, rel=1e-6)
 
 
 def test_sod_mass_constant_until_disturbance_reaches_ends():
