@@ -395,6 +395,15 @@ def main(argv=None):
         for levels, ev, shape in (((1, 1, 1), False, (256, 256, 128)), ((2, 2, 2), False, (128, 128, 128)),
                                   ((1, 3, 1), False, (256, 128, 128)), ((1, 3, 1), True, (256, 128, 128))):
             sweep.append(run_gpu3(levels, ev, *shape, a.storage, a.sweep_steps, 5))
+        # the 16-bit storages over the 2N+1 levels (same lattice and size)
+        for st in ("bf16_shifted", "bf16_shifted_sr"):
+            if st == a.storage:
+                continue
+            for lv in range(1, 8):
+                r = run_gpu(lv, a.nx, a.ny, st, a.sweep_steps, 5)
+                sweep.append({"lattice": "odd", "N": lv, "storage": st, "Q": r["Q"], "glups": round(r["glups"], 4),
+                              "achieved_GBs": round(r["achieved_GBs"], 4), "ms_per_step": round(r["ms_per_step"], 4),
+                              "frac": round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)})
     batched = None if a.no_batched else run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)
     served = None if a.no_served else run_served(a.served_seconds)
     solves = None if a.no_served else run_solves()

@@ -742,6 +742,16 @@ __host__ __device__ inline uint32_t step_seed(int64_t t)
     return (uint32_t)(x >> 32);
 }
 
+// An empty register constraint on every word: afterwards the compiler must
+// treat the words as changed (no instruction is emitted), so values derived
+// from them earlier are recomputed instead of kept live.
+template <int Q>
+__device__ __forceinline__ void opaque_words(uint32_t (&w)[Q])
+{
+#pragma unroll
+    for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(w[i]));
+}
+
 // ------------------------------------------------------------- kernels
 // One step of a node with 16-bit storage that takes no wall emission: the
 // populations stay packed two per register from the loads to the stores.
@@ -775,6 +785,11 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
     P regs{pk, h};
     float rho, jx, jy, ux, uy;
     density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
+    // With stochastic rounding, unpack again in the collision: holding all Q
+    // unpacked values beside the packed words (the compiler's choice) pushed
+    // the kernel into spills or accumulation registers (2.3-3.1x slower at 196
+    // and 225 velocities).  Round to nearest is faster left alone.
+    if constexpr (ST == ST_BF16SR) opaque_words(pk);
     collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
     constexpr int V = Axis<LX>::vmax;
     int pc = x + kGhost;
@@ -847,13 +862,24 @@ __global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
     step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, p.seed);
 }
 
+// Waves per SIMD to ask of the register allocator for the 16-bit kernels: two
+// up to 144 velocities; beyond, two waves would force large spills (the
+// populations of a node do not fit 256 registers beside the collision), so
+// the allocator is left free (one wave, no spills).
+template <int LX, int LY, int ST>
+constexpr int packed_waves()
+{
+    return Lat<LX, LY, ST>::Q <= 144 ? 2 : 1;
+}
+
 // The packed 16-bit interior rows, asking the register allocator for two
-// waves per SIMD: left to itself the scheduler sinks the packing of loaded
+// waves per SIMD up to 144 velocities: left to itself the scheduler sinks the packing of loaded
 // pairs to their use (hiding load latency) and ends a few registers above the
 // 256 that two waves allow, halving the bytes in flight of a memory-bound
 // kernel.
 template <int LX, int LY, int ST, int BCX, int BCY>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel_packed(KArgs p)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(packed_waves<LX, LY, ST>()))) void
+step_kernel_packed(KArgs p)
 {
     const int i = row_set_node<LY, ROWS_INTERIOR>(tile_index(p) * kBlock + (int)threadIdx.x, p.nx, p.ny);
     if (i < 0) return;

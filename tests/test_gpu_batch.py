@@ -195,3 +195,33 @@ def test_autotune_returns_a_candidate():
     best, results = batching.autotune(cfgs, steps=16, cands=cands)
     assert best in cands
     assert len(results) == len(cands) and all(sec > 0 for _, sec in results)
+
+
+PACKED_CASES = [
+    # 16-bit lattices stepped alone (interior rows in the packed kernel, its
+    # register budget chosen by the velocity count) and in a batch (the batch
+    # kernel, its own register allocation): the same node arithmetic
+    dict(dims=2, level_x=3, level_y=3, nx=4, ny=37, kn=0.1, bc_y="wall", wall_u=(-0.05, 0.05)),
+    dict(dims=2, level_x=5, level_y=5, nx=70, ny=23, tau=0.9, bc_y="wall", g=1e-5),
+    dict(dims=2, level_x=2, level_y=2, nx=96, ny=9, tau=0.8, g=1e-4),
+    dict(dims=2, level_x=4, level_y=4, nx=2, ny=20, tau=0.7),
+    dict(dims=2, level_x=1, level_y=3, even_y=True, nx=6, ny=41, kn=0.2, bc_y="wall", wall_u=(-0.03, 0.05)),
+    dict(dims=2, level_x=5, level_y=5, even_x=True, even_y=True, nx=40, ny=30, tau=1.1, bc_y="wall",
+         wall_u=(0.02, 0.0)),
+    dict(dims=2, level_x=6, level_y=6, nx=130, ny=30, tau=1.1, bc_y="wall", wall_u=(0.02, 0.0)),
+    dict(dims=2, level_x=7, level_y=7, nx=33, ny=30, tau=0.9, bc_y="wall", g=1e-5),
+]
+
+
+@pytest.mark.parametrize("storage", ["bf16_shifted", "bf16_shifted_sr"])
+@pytest.mark.parametrize("case", range(len(PACKED_CASES)))
+def test_16bit_alone_matches_batch_bitwise(case, storage):
+    cfg = dict(PACKED_CASES[case], storage=storage)
+    print("\n[batch] 16-bit alone vs batched: %s" % cfg, flush=True)
+    alone, batched = _solver(cfg), _solver(cfg)
+    for s in (alone, batched):
+        _init(s, cfg, 3 + case)
+    with glbm.Batch([batched], tile_nodes=64) as b:
+        b.step(25)
+    alone.step(25)
+    _assert_bitwise([alone], [batched], "16-bit %d %s" % (case, storage))
