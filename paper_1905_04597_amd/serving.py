@@ -64,6 +64,32 @@ def step_bytes(w: wl.Workload) -> int:
     return 2 * w.nodes * w.nvel * ELEM_BYTES[w.storage]
 
 
+def lane_of(w: wl.Workload, light_bytes: int, light_lanes: int) -> int:
+    """Lane of a request: the heavy lane (index light_lanes) when one step
+    moves at least light_bytes, else a light lane chosen by the kernel
+    variant (axes, storage, boundaries), so that the members of one variant
+    share a lane and its launches."""
+    if step_bytes(w) >= light_bytes:
+        return light_lanes
+    key = "%d/%d%s/%d%s/%s/%s/%s" % (w.dims, w.level_x, "e" if w.even_x else "", w.level_y,
+                                      "e" if w.even_y else "", w.storage, w.bc_x, w.bc_y)
+    return zlib.crc32(key.encode()) % light_lanes
+
+
+def admissible(waiting_bytes, in_use: float, budget: float, free_slots: int) -> int:
+    """How many requests at the head of a lane's queue to admit now, first
+    come first served: each needs its population bytes within the budget
+    beside those in use and a free slot; the first that does not fit stops
+    the admission (no overtaking)."""
+    n = 0
+    for nb in waiting_bytes:
+        if n >= free_slots or in_use + nb > budget:
+            break
+        in_use += nb
+        n += 1
+    return n
+
+
 def make_solver(w: wl.Workload, stream):
     """Create and initialise the solver of a request on `stream` (its buffers
     are allocated from that stream, so their reuse is ordered on it)."""
@@ -149,12 +175,7 @@ class Server:
         self.peak_in_use = 0
 
     def _lane_of(self, w) -> int:
-        if step_bytes(w) >= self.light_bytes:
-            return self.nlight
-        # the kernel variant: axes, storage, boundaries, row layout
-        key = "%d/%d%s/%d%s/%s/%s/%s/%d" % (w.dims, w.level_x, "e" if w.even_x else "", w.level_y,
-                                             "e" if w.even_y else "", w.storage, w.bc_x, w.bc_y, w.nx < 64)
-        return zlib.crc32(key.encode()) % self.nlight
+        return lane_of(w, self.light_bytes, self.nlight)
 
     def _keep(self, req) -> bool:
         k = self.keep_results
@@ -179,11 +200,10 @@ class Server:
             lane.leaving.append(a)
 
     def _admit(self, lane: _Lane, now: float):
-        while lane.waiting and len(lane.members) < lane.slots:
-            r = lane.waiting[0]
-            if self.in_use + r.nbytes > self.hbm_budget:
-                break
-            lane.waiting.popleft()
+        n = admissible((r.nbytes for r in lane.waiting), self.in_use, self.hbm_budget,
+                       lane.slots - len(lane.members))
+        for _ in range(n):
+            r = lane.waiting.popleft()
             s = make_solver(r.workload, lane.stream)
             r.admitted = now
             self.in_use += r.nbytes
