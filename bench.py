@@ -196,7 +196,7 @@ def run_batched(count: int = 512, steps: int = 2000, storage: str = "f32_shifted
                     "speed~U[0.01,0.1] c_s, %d steps each, seed 190504597" % (count, steps),
         "storage": storage, "instances": count, "nodes": nodes, "populations": pops,
         "schedule": best, "autotune_s": round(tune_s, 2),
-        "autotune_us_per_step": {"%(tile_nodes)d/%(order)s/g%(graph_steps)d/r%(resident_nodes)d" % o: round(sec * 1e6, 1)
+        "autotune_us_per_step": {"%(tile_nodes)d/%(order)s/g%(graph_steps)d/r%(resident_nodes)d/s%(streams)d" % o: round(sec * 1e6, 1)
                                  for o, sec in table},
         "batched": {"solves_per_s": round(count / batch_s, 2), "seconds": round(batch_s, 4),
                     "glups": round(nodes * steps / batch_s / 1e9, 3),

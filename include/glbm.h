@@ -215,6 +215,11 @@ typedef struct glbm_batch_options {
     int32_t resident_nodes; /* members of at most this many nodes are stepped by one
                                workgroup each, all steps of a chunk in one launch per
                                variant (small lattices: no launch per step); 0 = none */
+    int32_t streams;     /* kernel variants advance side by side on up to this many
+                            streams (1..8; 0 = 1): the batch's stream and streams - 1
+                            more that the batch creates (default priority), joined
+                            back into the batch's stream after every chunk; the
+                            launches of one variant stay in order on one stream */
 } glbm_batch_options;
 
 typedef struct glbm_batch glbm_batch_t;

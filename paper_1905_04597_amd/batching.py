@@ -2,7 +2,7 @@
 
 A :class:`~paper_1905_04597_amd.glbm.Batch` advances its members with one
 launch per kernel variant and step over a table of tiles (a tile is a run of
-nodes of one member), optionally replayed from a captured HIP graph.  Three
+nodes of one member), optionally replayed from a captured HIP graph.  Five
 choices shape the schedule:
 
 * ``tile_nodes`` - nodes per workgroup (64, 128 or 256).  Small tiles waste
@@ -16,6 +16,8 @@ choices shape the schedule:
 * ``resident_nodes`` - members up to this size are stepped by one workgroup
   each, every step of a chunk in one launch (a per-instance schedule: small
   lattices leave the per-step launches).
+* ``streams`` - kernel variants advance side by side on this many streams,
+  so that the tail of one variant's launch overlaps the others.
 
 :func:`autotune` times every candidate on scratch copies of the members
 (fresh lattices of the same configurations, initialised at rest) and
@@ -32,11 +34,12 @@ TILE_NODES = (64, 128, 256)
 ORDERS = ("member", "interleave", "largest_first")
 GRAPH_STEPS = (0, 32)
 RESIDENT_NODES = (0, 8192)
+STREAMS = (1, 4)
 
 
-def candidates(tiles=TILE_NODES, orders=ORDERS, graphs=GRAPH_STEPS, resident=RESIDENT_NODES):
-    return [dict(tile_nodes=t, order=o, graph_steps=g, resident_nodes=r)
-            for t, o, g, r in itertools.product(tiles, orders, graphs, resident)]
+def candidates(tiles=TILE_NODES, orders=ORDERS, graphs=GRAPH_STEPS, resident=RESIDENT_NODES, streams=STREAMS):
+    return [dict(tile_nodes=t, order=o, graph_steps=g, resident_nodes=r, streams=n)
+            for t, o, g, r, n in itertools.product(tiles, orders, graphs, resident, streams)]
 
 
 def time_batch(solvers, options: dict, steps: int, warmup: int = 2) -> float:

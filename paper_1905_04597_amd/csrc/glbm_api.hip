@@ -527,6 +527,11 @@ struct glbm_batch {
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
     bool planned;  // the tables match `members`
+    // side streams for the variants (opt.streams - 1 of them), the fork event
+    // recorded on exec and one join event per side stream
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t ev_fork;
 };
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -548,6 +553,9 @@ static void batch_free(glbm_batch *b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->own_stream) (void)hipStreamDestroy(b->exec);
+    for (auto ev : b->side_done) (void)hipEventDestroy(ev);
+    for (auto st : b->side) (void)hipStreamDestroy(st);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (auto *m : b->members) m->in_batch = false;
     delete b;
 }
@@ -558,24 +566,50 @@ static T *at(char *base, size_t off)
     return reinterpret_cast<T *>(base + off);
 }
 
-// One chunk of k steps: launches l = 0..k-1 of every row set, then the device
-// step counter advances by k.
+// One chunk of k steps: for each kernel variant, its resident launch and
+// launches l = 0..k-1 of its row sets, then the device step counter advances
+// by k.  Variants hold disjoint members, so they need no ordering between
+// them: with side streams, variant v runs on stream v mod S (the batch's
+// stream first), forked from and joined back into the batch's stream.
 static hipError_t batch_chunk(glbm_batch *b, int k)
 {
     int64_t *bstep = at<int64_t>(b->d_mem, 0);
     const int32_t *phase = at<int32_t>(b->d_mem, b->o_phase);
     const int64_t *t0 = at<int64_t>(b->d_mem, b->o_t0);
     const KArgs *args = at<KArgs>(b->d_mem, b->o_args);
-    for (auto &r : b->resident) {
-        hipError_t e = r.var->resident(at<int32_t>(b->d_mem, r.list), r.count, args, phase, t0, bstep, k, b->exec);
+    std::vector<const Variant *> vars;
+    for (auto &r : b->resident)
+        if (std::find(vars.begin(), vars.end(), r.var) == vars.end()) vars.push_back(r.var);
+    for (auto &r : b->sets)
+        if (std::find(vars.begin(), vars.end(), r.var) == vars.end()) vars.push_back(r.var);
+    const size_t S = std::min(b->side.size() + 1, vars.size());
+    hipError_t e = hipSuccess;
+    if (S > 1) {
+        e = hipEventRecord(b->ev_fork, b->exec);
+        for (size_t i = 0; e == hipSuccess && i + 1 < S; ++i) e = hipStreamWaitEvent(b->side[i], b->ev_fork, 0);
         if (e != hipSuccess) return e;
     }
-    for (int l = 0; l < k; ++l)
-        for (auto &r : b->sets) {
-            hipError_t e = r.var->batch(r.rows, at<BatchTile>(b->d_mem, r.tiles), r.ntiles, b->opt.tile_nodes, args,
-                                        phase, t0, bstep, l, b->exec);
-            if (e != hipSuccess) return e;
-        }
+    for (size_t v = 0; v < vars.size(); ++v) {
+        const size_t si = v % S;
+        hipStream_t st = si == 0 ? b->exec : b->side[si - 1];
+        for (auto &r : b->resident)
+            if (r.var == vars[v]) {
+                e = r.var->resident(at<int32_t>(b->d_mem, r.list), r.count, args, phase, t0, bstep, k, st);
+                if (e != hipSuccess) return e;
+            }
+        for (int l = 0; l < k; ++l)
+            for (auto &r : b->sets)
+                if (r.var == vars[v]) {
+                    e = r.var->batch(r.rows, at<BatchTile>(b->d_mem, r.tiles), r.ntiles, b->opt.tile_nodes, args,
+                                     phase, t0, bstep, l, st);
+                    if (e != hipSuccess) return e;
+                }
+    }
+    for (size_t i = 0; e == hipSuccess && i + 1 < S; ++i) {
+        e = hipEventRecord(b->side_done[i], b->side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->exec, b->side_done[i], 0);
+    }
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bump_counter, dim3(1), dim3(1), 0, b->exec, bstep, (int64_t)k);
     return hipGetLastError();
 }
@@ -762,9 +796,11 @@ int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_option
 {
     if (!out) return fail(GLBM_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    glbm_batch_options o = {256, GLBM_ORDER_MEMBER, 0, 0};
+    glbm_batch_options o = {256, GLBM_ORDER_MEMBER, 0, 0, 1};
     if (opt) o = *opt;
     if (o.tile_nodes == 0) o.tile_nodes = 256;
+    if (o.streams == 0) o.streams = 1;
+    if (o.streams < 1 || o.streams > 8) return fail(GLBM_ERR_INVALID, "streams must be 1..8");
     if (o.tile_nodes != 64 && o.tile_nodes != 128 && o.tile_nodes != 256)
         return fail(GLBM_ERR_INVALID, "tile_nodes must be 64, 128 or 256");
     if (o.order < GLBM_ORDER_MEMBER || o.order > GLBM_ORDER_LARGEST_FIRST)
@@ -788,9 +824,18 @@ int glbm_batch_create(glbm_t *const *members, int32_t n, const glbm_batch_option
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_staged, hipEventDisableTiming);
+    if (e == hipSuccess && o.streams > 1) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    for (int i = 1; e == hipSuccess && i < o.streams; ++i) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) b->side.push_back(st);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->side_done.push_back(ev);
+    }
     if (e != hipSuccess) {
         batch_free(b);
-        return hip_fail(e, "creating the batch stream");
+        return hip_fail(e, "creating the batch streams");
     }
     rc = plan(b, members, n);
     if (rc != GLBM_OK) {

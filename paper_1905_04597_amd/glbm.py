@@ -63,6 +63,7 @@ class BatchOptions(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("graph_steps", ctypes.c_int32),
         ("resident_nodes", ctypes.c_int32),
+        ("streams", ctypes.c_int32),
     ]
 
 
@@ -307,7 +308,7 @@ class Batch:
     can be observed while in the batch; ``close()`` hands them back."""
 
     def __init__(self, solvers, tile_nodes: int = 256, order: str = "member", graph_steps: int = 0, stream=None,
-                 resident_nodes: int = 0):
+                 resident_nodes: int = 0, streams: int = 1):
         import torch
 
         if not solvers:
@@ -318,8 +319,8 @@ class Batch:
         self.device = self.solvers[0].device
         self.stream = stream if stream is not None else self.solvers[0].stream
         self.options = {"tile_nodes": int(tile_nodes), "order": order, "graph_steps": int(graph_steps),
-                        "resident_nodes": int(resident_nodes)}
-        opt = BatchOptions(int(tile_nodes), ORDER[order], int(graph_steps), int(resident_nodes))
+                        "resident_nodes": int(resident_nodes), "streams": int(streams)}
+        opt = BatchOptions(int(tile_nodes), ORDER[order], int(graph_steps), int(resident_nodes), int(streams))
         arr = (ctypes.c_void_p * len(self.solvers))(*[s._h.value for s in self.solvers])
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

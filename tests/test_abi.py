@@ -129,6 +129,10 @@ def test_batch_entry_points_reject_bad_arguments_without_touching_the_gpu():
     opt = glbm.BatchOptions(128, 1, 0, -5)
     assert lib.glbm_batch_create(None, 0, ctypes.byref(opt), None, ctypes.byref(out)) == -1
     assert "resident_nodes" in lib.glbm_last_error().decode()
+    for streams in (9, -1):
+        opt = glbm.BatchOptions(128, 1, 0, 0, streams)
+        assert lib.glbm_batch_create(None, 0, ctypes.byref(opt), None, ctypes.byref(out)) == -1
+        assert "streams" in lib.glbm_last_error().decode()
     assert lib.glbm_batch_create(None, 0, None, None, ctypes.byref(out)) == -1
     assert "at least one member" in lib.glbm_last_error().decode()
     assert lib.glbm_batch_create(None, 1, None, None, None) == -1

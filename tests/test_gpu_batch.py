@@ -82,6 +82,10 @@ def _assert_bitwise(alone, batched, what):
     # the others in tiles
     dict(tile_nodes=128, order="interleave", graph_steps=0, resident_nodes=1000),
     dict(tile_nodes=64, order="member", graph_steps=6, resident_nodes=4000),
+    # kernel variants side by side on several streams (plain launches, and
+    # captured into a graph with the fork and join)
+    dict(tile_nodes=128, order="interleave", graph_steps=0, streams=4),
+    dict(tile_nodes=64, order="member", graph_steps=6, resident_nodes=4000, streams=3),
 ])
 def test_batch_bitwise_equals_alone(opts):
     print("\n[batch] mixed members, options %s" % opts, flush=True)
@@ -115,7 +119,8 @@ def test_batch_update_joins_and_leaves_bitwise():
     for members, k in schedule:
         sol = [batched[i] for i in members]
         if b is None:
-            b = glbm.Batch(sol, tile_nodes=64, order="interleave", graph_steps=3, stream=stream, resident_nodes=500)
+            b = glbm.Batch(sol, tile_nodes=64, order="interleave", graph_steps=3, stream=stream, resident_nodes=500,
+                           streams=4)
         else:
             b.update(sol)
         b.step(k)
