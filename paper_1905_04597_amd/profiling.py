@@ -52,6 +52,30 @@ def counter(db_path: str, name: str):
     return {key: statistics.median(vs) for key, vs in by.items()}
 
 
+def batched_busy(trace: str):
+    """Microseconds during which at least one batched step kernel ran (the
+    union of their dispatch intervals), and the number of steps (launches of
+    the most launched level)."""
+    db = sqlite3.connect(trace)
+    iv = sorted((int(a), int(b)) for a, b in db.execute(
+        "select start, end from kernels where name like '%batch_step_kernel%'"))
+    calls = {}
+    for (name,) in db.execute("select name from kernels where name like '%batch_step_kernel%'"):
+        calls[name] = calls.get(name, 0) + 1
+    busy, cur_a, cur_b = 0, None, None
+    for a, b in iv:
+        if cur_b is None or a > cur_b:
+            if cur_b is not None:
+                busy += cur_b - cur_a
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    if cur_b is not None:
+        busy += cur_b - cur_a
+    steps = max(calls.values()) if calls else 0
+    return busy / 1e3, steps
+
+
 def batched_summary(trace: str, command: str, count: int = 512, storage: str = "f32_shifted"):
     """Per-level averages of the batched step kernel over the channel sweep:
     each launch steps every instance of one level once, so its algorithmic
@@ -91,8 +115,14 @@ def batched_summary(trace: str, command: str, count: int = 512, storage: str = "
             fh.write("| %d | %d | %.1f | %.4g | %.0f |\n" % (lx, calls, avg, b, gbs))
         tot_us = sum(r[2] for r in rows)
         tot_b = sum(r[3] for r in rows)
-        fh.write("\nOne step of the whole sweep: %.1f us of batched kernels for %.4g algorithmic bytes, "
-                 "%.0f GB/s.\n" % (tot_us, tot_b, tot_b / (tot_us * 1e-6) / 1e9))
+        busy_us, steps = batched_busy(trace)
+        fh.write("\nSum of the per-level launch times: %.1f us per step (launches of different levels overlap "
+                 "when the batch runs its variants on several streams, each then taking longer).\n" % tot_us)
+        if steps:
+            fh.write("\nOne step of the whole sweep: %.1f us with batched kernels running (union of their "
+                     "intervals over the %d batched steps of the run, the autotuner's trials of every schedule "
+                     "included) for %.4g algorithmic bytes, %.0f GB/s.\n"
+                     % (busy_us / steps, steps, tot_b, tot_b / (busy_us / steps * 1e-6) / 1e9))
         fh.write("- kernel source hash: %s\n" % kernel_source_hash())
     print(path)
 
