@@ -156,18 +156,22 @@ class Server:
     slots: most active requests per (light, heavy) lane.
     resident_nodes: light-lane members of at most this many nodes run
     resident (glbm_batch_options.resident_nodes).
+    streams: streams per lane over which a lane's kernel variants advance side
+    by side (glbm_batch_options.streams); (light, heavy).
     keep_results: True, or a set of request ids, whose device moments
     {rho, ux, uy, T, pxy} are kept in Request.result."""
 
     def __init__(self, hbm_budget: float = 200e9, light_bytes: int = 64 << 20, light_lanes: int = 3,
                  chunks=(50, 20), slots=(4096, 256), tile_nodes: int = 128, order: str = "interleave",
-                 resident_nodes: int = 2048, keep_results: bool = False, clock=time.perf_counter):
+                 resident_nodes: int = 2048, streams=(1, 1), keep_results: bool = False,
+                 clock=time.perf_counter):
         self.hbm_budget = float(hbm_budget)
         self.light_bytes = int(light_bytes)
         self.keep_results = keep_results
         self.clock = clock
-        light = dict(tile_nodes=tile_nodes, order=order, graph_steps=0, resident_nodes=resident_nodes)
-        heavy = dict(tile_nodes=tile_nodes, order=order, graph_steps=0, resident_nodes=0)
+        light = dict(tile_nodes=tile_nodes, order=order, graph_steps=0, resident_nodes=resident_nodes,
+                     streams=int(streams[0]))
+        heavy = dict(tile_nodes=tile_nodes, order=order, graph_steps=0, resident_nodes=0, streams=int(streams[1]))
         self.nlight = int(light_lanes)
         self.lanes = [_Lane(i, chunks[0], slots[0], light) for i in range(self.nlight)]
         self.lanes.append(_Lane(self.nlight, chunks[1], slots[1], heavy))
