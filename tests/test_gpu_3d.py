@@ -119,3 +119,51 @@ def test_3d_members_are_refused_by_batches():
     s.init_fields()
     with pytest.raises(glbm.GlbmError, match="one- and two-dimensional"):
         glbm.Batch([s])
+
+
+BENCH_SHAPES = [
+    # the three-dimensional lattices and shapes of the bench sweep
+    ((1, 1, 1), False, (256, 256, 128)),
+    ((2, 2, 2), False, (128, 128, 128)),
+    ((1, 3, 1), False, (256, 128, 128)),
+    ((1, 3, 1), True, (256, 128, 128)),
+]
+
+
+@pytest.mark.parametrize("levels,even_y,shape", BENCH_SHAPES, ids=["d3q27", "g_d3q125", "d1q3xd1q7xd1q3",
+                                                                   "d1q3xd1q8xd1q3"])
+def test_3d_bench_shapes_against_oracle_columns(levels, even_y, shape):
+    """The bench's three-dimensional runs at full size (walls across y,
+    g = 1e-5, Kn = 0.1, from rest, FP32 deviation storage; here with moving
+    walls too, so that the flow is not tiny), 300 steps.  The data stay
+    uniform in x and z, so every (x, z) column of the GPU state must be
+    bitwise the same, and equal to the oracle's column of a 2 x ny x 2
+    lattice within 1e-5."""
+    import torch
+
+    (lx, ly, lz), (nx, ny, nz), steps = levels, shape, 300
+    th_y = (4 * ly + 3) / 3.0 if even_y else ly / 3.0
+    U = 0.05 * math.sqrt(th_y)
+    print("\n[3d] bench shape %s levels %s even_y %s" % (shape, levels, even_y), flush=True)
+    cfg = glbm.make_config(3, lx, ly, nx, ny, kn=0.1, bc_y="wall", wall_u=(-U, U), g=1e-5, storage="f32_shifted",
+                           even_y=even_y, level_z=lz, nz=nz)
+    gpu = glbm.Solver(cfg)
+    gpu.init_fields()
+    gpu.step(steps)
+    m = gpu.moments()
+    torch.cuda.synchronize()
+    orc = oracle.OracleSolver(3, lx, ly, 2, ny, kn=0.1, bc_y=oracle.BC_WALL, wall_u=(-U, U), g=1e-5,
+                              even_y=even_y, level_z=lz, nz=2)
+    orc.init_fields()
+    orc.step(steps)
+    ref = {k: v[0, :, 0] for k, v in orc.moments().items()}
+    cols = [(0, 0), (nx - 1, nz - 1), (nx // 2, 1), (3, nz // 2 + 1), (nx - 5, 7)]
+    got = {k: v.cpu().numpy() for k, v in m.items()}
+    for x, z in cols[1:]:
+        for k in got:
+            assert np.array_equal(got[k][z, :, x], got[k][0, :, 0]), (k, x, z)
+    col = {k: v[0, :, 0].astype(np.float64) for k, v in got.items()}
+    errs = compare_moments(ref, col, max(th_y, lx / 3.0, lz / 3.0))
+    print("[3d] t=%d column vs oracle %s" % (steps, fmt(errs)), flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+    gpu.close()
