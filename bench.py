@@ -216,9 +216,10 @@ def run_solves():
     """Time per solve of the Sod tube (D1Q7, 2000 nodes, Kn = 0.01, 1000 steps)
     and the Couette channels (G-D2Q49, 4 x 256, Kn 0.01 / 0.1 / 1 / 10, run for
     the number of steps at which the FP64 reference reached a residual of
-    1e-10: 15300 / 2600 / 5000 / 40500): one launch per step, and the same
-    solve as a one-member resident batch (one workgroup, every step of the
-    solve in one launch).  Both give bitwise the same populations (checked)."""
+    1e-10: 15300 / 2600 / 5000 / 40500): one launch per step; the same solve
+    as a one-member batch of 64-node tiles replayed from 100-step HIP graphs;
+    and as a one-member resident batch (one workgroup, every step of the solve
+    in one launch).  All give bitwise the same populations (checked)."""
     import numpy as np
     import torch
     from paper_1905_04597_amd import glbm
@@ -231,7 +232,7 @@ def run_solves():
     for name, w, steps in cases:
         times = {}
         pops = []
-        for mode in ("per_step_launch", "resident"):
+        for mode in ("per_step_launch", "graph", "resident"):
             s = glbm.solver_for(w)
             if w.init == "sod":
                 rho = wl.sod_density(w.nx, *w.end_rho)
@@ -243,6 +244,9 @@ def run_solves():
             if mode == "resident":
                 with glbm.Batch([s], resident_nodes=w.nodes) as b:
                     b.step(steps)
+            elif mode == "graph":
+                with glbm.Batch([s], tile_nodes=64, graph_steps=100) as b:
+                    b.step(steps)
             else:
                 s.step(steps)
             torch.cuda.synchronize()
@@ -251,7 +255,7 @@ def run_solves():
             s.close()
         out[name] = {"steps": steps, "nodes": w.nodes, "velocities": w.nvel,
                      "ms_per_solve": {k: round(v * 1e3, 2) for k, v in times.items()},
-                     "bitwise_equal": bool(torch.equal(pops[0], pops[1]))}
+                     "bitwise_equal": all(bool(torch.equal(pops[0], p)) for p in pops[1:])}
     return out
 
 
