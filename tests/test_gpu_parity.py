@@ -25,6 +25,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 from paper_1905_04597_amd import workloads as wl
 from tests.gpu_common import BOUND, compare_moments, fmt, gpu_moments, initialise, make_pair, rel_err
 
@@ -82,6 +83,13 @@ CASES = {
     "even_d2q196_walls_fields": (dict(dims=2, level_x=6, level_y=6, even_x=True, even_y=True, nx=70, ny=28,
                                       tau=0.65, bc_y="wall", wall_u=(-0.03, 0.03), g=2e-5), "fields", 5,
                                  ("f32_shifted",)),
+    # degenerate shapes: one column (every x velocity wraps onto the node
+    # itself) with the fewest rows walls allow (ny = 2N), and with the fewest
+    # rows a periodic y allows (ny = N)
+    "d2q49_walls_nx1_ny6_min": (dict(dims=2, level_x=3, level_y=3, nx=1, ny=6, kn=0.3, bc_y="wall",
+                                     wall_u=(-0.04, 0.06), g=1e-4), "fields", 50, ALL),
+    "d2q121_periodic_nx1_ny5_min": (dict(dims=2, level_x=5, level_y=5, nx=1, ny=5, tau=0.8, g=1e-4),
+                                    "populations", 30, F32),
 }
 
 PARAMS = [(name, st) for name, (_, _, _, sts) in CASES.items() for st in sts]
@@ -169,3 +177,43 @@ def test_narrow_channel_matches_wide_channel_bitwise(level, storage):
     narrow, wide = cols
     for x in range(64):
         assert np.array_equal(wide[:, :, x], narrow[:, :, x % 4]), x
+
+
+def test_largest_buffer_channel_columns():
+    """The largest lattice one population buffer holds: G-D2Q225 (N = 7) in
+    FP32, 4096 x 1165 nodes (4,294,656,000 bytes of the 4 GiB that 32-bit
+    buffer offsets address).  An x-uniform channel (moving walls, force) for
+    20 steps: every sampled column bitwise equal to the first, and the first
+    within 1e-5 of the oracle's 2-wide channel."""
+    import torch
+    from paper_1905_04597_amd import glbm
+
+    N, nx, ny, steps = 7, 4096, 1165, 20
+    U = 0.05 * math.sqrt(N / 3.0)
+    params = dict(dims=2, level_x=N, level_y=N, nx=nx, ny=ny, kn=0.1, bc_y="wall", wall_u=(-U, U), g=1e-5)
+    cfg = glbm.make_config(**params, storage="f32_shifted")
+    assert glbm.population_bytes(cfg) == 4294656000
+    print("\n[parity] largest buffer: G-D2Q225 %dx%d, %d steps" % (nx, ny, steps), flush=True)
+    gpu = glbm.Solver(cfg)
+    y = (np.arange(ny) + 0.5) / ny
+    prof = [1 + 0.02 * np.cos(2 * np.pi * y), 0.05 * np.sin(2 * np.pi * y), 0.01 * np.cos(4 * np.pi * y)]
+    gpu.init_fields(*[np.repeat(v.astype(np.float32)[:, None], nx, axis=1) for v in prof])
+    gpu.step(steps)
+    m = gpu.moments()
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in m.items()}
+    for x in (1, 2047, 2048, 4000, nx - 1):
+        for k in got:
+            assert np.array_equal(got[k][:, x], got[k][:, 0]), (k, x)
+    pops = gpu.populations()
+    torch.cuda.synchronize()
+    last = pops[-1].cpu().numpy()  # the last plane, at the top of the buffer
+    assert np.array_equal(last[:, nx - 1], last[:, 0])
+    orc = oracle.OracleSolver(2, N, N, 2, ny, kn=0.1, bc_y=oracle.BC_WALL, wall_u=(-U, U), g=1e-5)
+    orc.init_fields(*[np.repeat(v[:, None], 2, axis=1) for v in prof])
+    orc.step(steps)
+    ref = {k: v[:, :1] for k, v in orc.moments().items()}
+    errs = compare_moments(ref, {k: got[k][:, :1].astype(np.float64) for k in got}, N / 3.0)
+    print("[parity] largest buffer: column vs oracle %s" % fmt(errs), flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+    gpu.close()
