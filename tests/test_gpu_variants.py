@@ -1,0 +1,127 @@
+"""Every kernel variant the library builds, once, against the FP64 oracle.
+
+The variants: one dimension (G-D1Q(2N+1) and G-D1Q(2N+2), N = 1..7,
+periodic or fixed equilibrium ends), two dimensions (the symmetric products,
+N = 1..7 and N = 1..6 for the even axis; periodic y or walls), the mixed
+channel lattices D1Q3 x G-D1Q(2N+1) (N = 2..7) and D1Q3 x G-D1Q(2N+2)
+(N = 1..7) with walls, and the three-dimensional lattices (D3Q27, G-D3Q125,
+D1Q3 x G-D1Q5/Q7/Q6/Q8 x D1Q3; periodic y or walls), each in the four
+storages.  Each runs a small seeded case (random shape within what the
+variant allows, random relaxation time, force and wall speeds, random
+fields) for 6 steps; moments and populations are compared with the oracle.
+
+Bounds per storage for these short runs: FP32 deviation storage 1e-5 (the
+stated tolerance), plain FP32 2e-4 (it re-rounds f ~ W every step; up to
+1.3e-4 measured on the largest lattices), BF16 5e-2 per node (8 significand
+bits).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04597_amd import glbm
+from tests.gpu_common import compare_moments, fmt, rel_err
+
+pytestmark = pytest.mark.gpu
+
+STORAGES = ("f32_shifted", "f32", "bf16_shifted", "bf16_shifted_sr")
+BOUND = {"f32_shifted": 1e-5, "f32": 2e-4, "bf16_shifted": 5e-2, "bf16_shifted_sr": 5e-2}
+
+
+def _axes():
+    """(dims, (level, even) per axis, bc_x, bc_y) of every built variant."""
+    out = []
+    for even in (False, True):
+        for n in range(1, 8):
+            for bcx in ("periodic", "eq_ends"):
+                out.append((1, ((n, even),), bcx, "periodic"))
+    for even, top in ((False, 7), (True, 6)):
+        for n in range(1, top + 1):
+            for bcy in ("periodic", "wall"):
+                out.append((2, ((n, even), (n, even)), "periodic", bcy))
+    for n in range(2, 8):
+        out.append((2, ((1, False), (n, False)), "periodic", "wall"))
+    for n in range(1, 8):
+        out.append((2, ((1, False), (n, True)), "periodic", "wall"))
+    for lat in (((1, False),) * 3, ((2, False),) * 3, ((1, False), (2, False), (1, False)),
+                ((1, False), (3, False), (1, False)), ((1, False), (2, True), (1, False)),
+                ((1, False), (3, True), (1, False))):
+        for bcy in ("periodic", "wall"):
+            out.append((3, lat, "periodic", bcy))
+    return out
+
+
+CASES = [(a, st) for a in _axes() for st in STORAGES]
+
+
+def _name(case):
+    (dims, axes, bcx, bcy), st = case
+    ax = "x".join("%s%d" % ("e" if e else "o", n) for n, e in axes)
+    return "%dd-%s-%s-%s-%s" % (dims, ax, bcx, bcy, st)
+
+
+def _reach(n, even):
+    return 2 * n + 1 if even else n
+
+
+def _theta(n, even):
+    return (4 * n + 3) / 3.0 if even else n / 3.0
+
+
+@pytest.mark.parametrize("idx", range(len(CASES)), ids=[_name(c) for c in CASES])
+def test_variant_against_oracle(idx):
+    import torch
+
+    (dims, axes, bcx, bcy), storage = CASES[idx]
+    rng = np.random.default_rng(1000 + idx)
+    (nxl, exx) = axes[0]
+    (nyl, eyy) = axes[1] if dims >= 2 else (0, False)
+    (nzl, ezz) = axes[2] if dims == 3 else (0, False)
+    rx = _reach(nxl, exx)
+    nx = int(rng.integers(rx if bcx == "eq_ends" else 1, rx + (30 if dims == 1 else 12)))
+    ny = nz = 1
+    if dims >= 2:
+        ry = _reach(nyl, eyy)
+        lo = 2 * ry if bcy == "wall" else ry
+        ny = int(rng.integers(lo, lo + (12 if dims == 2 else 5)))
+    if dims == 3:
+        rz = _reach(nzl, ezz)
+        nz = int(rng.integers(rz, rz + 4))
+    tau = float(rng.uniform(0.6, 1.5))
+    g = float(rng.choice([0.0, 1e-4]))
+    cs_y = math.sqrt(_theta(nyl, eyy)) if dims >= 2 else 0.0
+    wall_u = tuple(float(v) for v in rng.uniform(-0.05, 0.05, 2) * cs_y) if bcy == "wall" else (0.0, 0.0)
+    end_rho = (1.0 + float(rng.uniform(0, 0.2)), 1.0 - float(rng.uniform(0, 0.2))) if bcx == "eq_ends" else (1, 1)
+    shape = (nz, ny, nx) if dims == 3 else (ny, nx)
+    print("\n[variants] %s shape %s tau %.3f g %g walls %s" % (_name(CASES[idx]), shape, tau, g, wall_u),
+          flush=True)
+    cfg = glbm.make_config(dims, nxl, nyl, nx, ny, tau=tau, bc_x=bcx, bc_y=bcy, wall_u=wall_u, end_rho=end_rho,
+                           g=g, storage=storage, even_x=exx, even_y=eyy, level_z=nzl, nz=nz, even_z=ezz)
+    gpu = glbm.Solver(cfg)
+    orc = oracle.OracleSolver(dims, nxl, nyl, nx, ny, tau=tau,
+                              bc_x=oracle.BC_EQ_ENDS if bcx == "eq_ends" else oracle.BC_PERIODIC,
+                              bc_y=oracle.BC_WALL if bcy == "wall" else oracle.BC_PERIODIC, wall_u=wall_u,
+                              end_rho=end_rho, g=g, even_x=exx, even_y=eyy, level_z=nzl, nz=nz, even_z=ezz)
+    fields = [(1.0 + 0.05 * rng.uniform(-1, 1, shape)).astype(np.float32)]
+    for _ in range(dims):
+        fields.append((0.05 * rng.uniform(-1, 1, shape)).astype(np.float32))
+    gpu.init_fields(*fields)
+    orc.init_fields(*[f.astype(np.float64) for f in fields])
+    steps = 6
+    gpu.step(steps)
+    orc.step(steps)
+    m = gpu.moments()
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in m.items()}
+    ref = orc.moments()
+    th = max(_theta(n, e) for n, e in axes)
+    errs = compare_moments(ref, got, th)
+    fe = rel_err(gpu.populations().cpu().numpy(), orc.populations())
+    print("[variants] t=%d %s populations %.2e" % (steps, fmt(errs), fe), flush=True)
+    tol = BOUND[storage]
+    assert max(errs.values()) <= tol and fe <= tol, (errs, fe)
+    sg, so = gpu.stats(), orc.stats()
+    assert abs(sg["mass"] - so["mass"]) <= min(tol, 1e-5) * abs(so["mass"]) or storage.startswith("bf16")
+    gpu.close()
