@@ -9,6 +9,9 @@ D1Q3 x G-D1Q5/Q7/Q6/Q8 x D1Q3; periodic y or walls), each in the four
 storages.  Each runs a small seeded case (random shape within what the
 variant allows, random relaxation time, force and wall speeds, random
 fields) for 6 steps; moments and populations are compared with the oracle.
+The one- and two-dimensional variants also run in a tiled batch (with a
+captured graph) and as a resident batch member, bitwise equal to the
+lattice stepped alone (the batch kernels are instantiations of their own).
 
 Bounds per storage for these short runs: FP32 deviation storage 1e-5 (the
 stated tolerance), plain FP32 2e-4 (it re-rounds f ~ W every step; up to
@@ -125,3 +128,48 @@ def test_variant_against_oracle(idx):
     sg, so = gpu.stats(), orc.stats()
     assert abs(sg["mass"] - so["mass"]) <= min(tol, 1e-5) * abs(so["mass"]) or storage.startswith("bf16")
     gpu.close()
+
+
+BATCHED = [i for i, ((dims, _, _, _), _) in enumerate(CASES) if dims <= 2]
+
+
+@pytest.mark.parametrize("idx", BATCHED, ids=[_name(CASES[i]) for i in BATCHED])
+def test_variant_batched_and_resident_bitwise(idx):
+    """The batch kernels of every one- and two-dimensional variant: the same
+    case stepped alone, in a tiled batch (with a captured graph) and as a
+    resident member gives bitwise the same populations."""
+    import torch
+
+    (dims, axes, bcx, bcy), storage = CASES[idx]
+    rng = np.random.default_rng(2000 + idx)
+    (nxl, exx) = axes[0]
+    (nyl, eyy) = axes[1] if dims == 2 else (0, False)
+    rx = _reach(nxl, exx)
+    nx = int(rng.integers(rx if bcx == "eq_ends" else 1, rx + 30))
+    ny = 1
+    if dims == 2:
+        ry = _reach(nyl, eyy)
+        lo = 2 * ry if bcy == "wall" else ry
+        ny = int(rng.integers(lo, lo + 12))
+    wall_u = (0.03, -0.02) if bcy == "wall" else (0.0, 0.0)
+    end_rho = (1.1, 0.9) if bcx == "eq_ends" else (1, 1)
+    cfg = glbm.make_config(dims, nxl, nyl, nx, ny, tau=0.9, bc_x=bcx, bc_y=bcy, wall_u=wall_u, end_rho=end_rho,
+                           g=1e-4, storage=storage, even_x=exx, even_y=eyy)
+    print("\n[variants] batched %s shape (%d, %d)" % (_name(CASES[idx]), ny, nx), flush=True)
+    fields = [(1.0 + 0.05 * rng.uniform(-1, 1, (ny, nx))).astype(np.float32)]
+    fields += [(0.05 * rng.uniform(-1, 1, (ny, nx))).astype(np.float32) for _ in range(dims)]
+    solvers = [glbm.Solver(cfg) for _ in range(3)]
+    for s in solvers:
+        s.init_fields(*fields)
+    steps = 7
+    solvers[0].step(steps)
+    with glbm.Batch([solvers[1]], tile_nodes=64, graph_steps=3) as b:
+        b.step(steps)
+    with glbm.Batch([solvers[2]], resident_nodes=nx * ny) as b:
+        b.step(steps)
+    pops = [s.populations() for s in solvers]
+    torch.cuda.synchronize()
+    assert torch.equal(pops[0], pops[1]), "tiled batch"
+    assert torch.equal(pops[0], pops[2]), "resident"
+    for s in solvers:
+        s.close()
