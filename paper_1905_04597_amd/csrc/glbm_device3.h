@@ -132,13 +132,16 @@ __device__ __forceinline__ float wall_absorbed3(const KArgs &p, rsrc_t rs, const
 }
 
 // Pre-collision populations of node (x, y, z): pulled, or emitted by a wall.
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+// INTERIOR: the node is at least the fastest y velocity away from both walls,
+// so nothing is emitted into it and the pull has no branches (all its loads
+// can be in flight together).
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR = false>
 __device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y, int z,
                                       float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q])
 {
     using L = Lat3<LX, LY, LZ, ST>;
     float rw[2] = {0.0f, 0.0f};
-    if constexpr (BCY == BCY_WALL) {
+    if constexpr (BCY == BCY_WALL && !INTERIOR) {
         constexpr double jp = kYZ<LY, LZ>.jplus;
         constexpr int reach = Axis<LY>::vmax;
         if (y < reach) rw[0] = wall_absorbed3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z, nullptr) / (float)(jp * p.fwsum[0]);
@@ -153,8 +156,8 @@ __device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX,
             int ys = y - cb;
             bool emit = false;
             if constexpr (BCY == BCY_WALL) {
-                if constexpr (cb > 0) emit = ys < 0;
-                if constexpr (cb < 0) emit = ys >= p.ny;
+                if constexpr (cb > 0 && !INTERIOR) emit = ys < 0;
+                if constexpr (cb < 0 && !INTERIOR) emit = ys >= p.ny;
             } else {
                 if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
                 if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
@@ -315,19 +318,35 @@ __device__ __forceinline__ void node_xyz(const KArgs &p, int i, int &x, int &y, 
     y = r - z * p.ny;
 }
 
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+// One step over a set of rows (StepRows): every row, the rows of each z plane
+// that take no wall emission, or the rows next to the walls (as many as the
+// fastest y velocity reaches), so that the interior pull has no branches.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, int ROWS>
 __global__ __launch_bounds__(kBlock) void step3_kernel(KArgs p)
 {
     using L = Lat3<LX, LY, LZ, ST>;
-    const int i = tile_index(p) * kBlock + (int)threadIdx.x;
-    if (i >= p.nodes) return;
+    const int j = tile_index(p) * kBlock + (int)threadIdx.x;
     int x, y, z;
-    node_xyz(p, i, x, y, z);
+    if constexpr (ROWS == ROWS_ALL) {
+        if (j >= p.nodes) return;
+        node_xyz(p, j, x, y, z);
+    } else {
+        constexpr int R = Axis<LY>::vmax;
+        const int rows = ROWS == ROWS_INTERIOR ? p.ny - 2 * R : 2 * R;
+        const int per = rows * p.nx;
+        if (j >= per * p.nz) return;
+        z = j / per;
+        const int r = j - z * per;
+        const int yr = r / p.nx;
+        x = r - yr * p.nx;
+        y = ROWS == ROWS_INTERIOR ? yr + R : (yr < R ? yr : p.ny - 2 * R + yr);
+    }
+    const int i = (z * p.ny + y) * p.nx + x;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
     const XAddr<LX, L::EB, BCX> xa(x, p.nx);
     float v[L::QZ][L::QY][L::QX];
-    pull3<LX, LY, LZ, ST, BCX, BCY>(p, rs, xa, y, z, v);
+    pull3<LX, LY, LZ, ST, BCX, BCY, ROWS == ROWS_INTERIOR>(p, rs, xa, y, z, v);
     float rho, jx, jy, jz;
     moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
     const float inv = 1.0f / rho;

@@ -12,7 +12,19 @@ template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
 struct Launchers3 {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
-        hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        if constexpr (BCY == BCY_WALL) {
+            // rows that take no wall emission (branch-free pull), then the
+            // rows next to the walls
+            constexpr int R = Axis<LY>::vmax;
+            const int interior = a.nz * (a.ny - 2 * R) * a.nx, walls = a.nz * 2 * R * a.nx;
+            if (interior > 0)
+                hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY, ROWS_INTERIOR>),
+                                   dim3((interior + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY, ROWS_WALLS>),
+                               dim3((walls + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY, ROWS_ALL>), dim3(grid), dim3(kBlock), 0, s, a);
+        }
         return hipGetLastError();
     }
     static hipError_t observe(const KArgs &a, int grid, hipStream_t s)
