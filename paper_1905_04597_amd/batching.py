@@ -16,8 +16,9 @@ choices shape the schedule:
 * ``resident_nodes`` - members up to this size are stepped by one workgroup
   each, every step of a chunk in one launch (a per-instance schedule: small
   lattices leave the per-step launches).
-* ``streams`` - kernel variants advance side by side on this many streams,
-  so that the tail of one variant's launch overlaps the others.
+* ``streams`` - kernel variants advance side by side on up to this many
+  streams (1, 4 or 8; at most one per variant), so that the tail of one
+  variant's launch overlaps the others.
 
 :func:`autotune` times every candidate on scratch copies of the members
 (fresh lattices of the same configurations, initialised at rest) and
@@ -34,7 +35,7 @@ TILE_NODES = (64, 128, 256)
 ORDERS = ("member", "interleave", "largest_first")
 GRAPH_STEPS = (0, 32)
 RESIDENT_NODES = (0, 8192)
-STREAMS = (1, 4)
+STREAMS = (1, 4, 8)
 
 
 def candidates(tiles=TILE_NODES, orders=ORDERS, graphs=GRAPH_STEPS, resident=RESIDENT_NODES, streams=STREAMS):

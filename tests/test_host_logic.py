@@ -120,6 +120,6 @@ def test_summary_of_latencies():
 
 def test_autotuner_candidates():
     c = batching.candidates()
-    assert len(c) == 3 * 3 * 2 * 2 * 2
+    assert len(c) == 3 * 3 * 2 * 2 * 3
     assert len({tuple(sorted(d.items())) for d in c}) == len(c)
     assert all(d["tile_nodes"] in (64, 128, 256) for d in c)
