@@ -309,7 +309,7 @@ def run_served(duration: float = 12.0, warm: float = 2.0, sample: int = 16, loop
     }
 
 
-def cpu_baseline(level: int = 5, nx: int = 64, ny: int = 1024, steps: int = 40):
+def cpu_baseline(level: int = 5, nx: int = 64, ny: int = 1024, steps: int = 100):
     """The FP64 oracle (single-threaded C) on a bounded sample of the workload:
     the same level, wall distance and parameters, a narrower channel."""
     import oracle
