@@ -336,14 +336,14 @@ struct KArgs {
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous run of tiles so that the halo lines two neighbouring tiles share
 // meet in the same L2.
-__device__ __forceinline__ int tile_index(const KArgs &p)
+__device__ __forceinline__ int tile_of(int b, int G, int remap)
 {
-    const int b = blockIdx.x, G = gridDim.x;
-    if (!p.remap) return b;
+    if (!remap) return b;
     const int G8 = G & ~7;
     if (b >= G8) return b;
     return (b & 7) * (G8 >> 3) + (b >> 3);
 }
+__device__ __forceinline__ int tile_index(const KArgs &p) { return tile_of(blockIdx.x, gridDim.x, p.remap); }
 
 // ------------------------------------------------- per-axis equilibrium
 // F_n(u), n = -N..N: N-fold convolution of the D1Q3 equilibrium at v = u/N,
@@ -862,6 +862,23 @@ __global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
     step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, p.seed);
 }
 
+// Blocks of the wall rows in a merged 16-bit launch (a multiple of 8).
+template <int LY>
+__host__ __device__ constexpr int wall_blocks(int nx)
+{
+    return ((2 * Axis<LY>::vmax * nx + kBlock - 1) / kBlock + 7) / 8 * 8;
+}
+
+// Whether the 16-bit interior and wall rows share one launch: where the wall
+// rows' FP32 registers fit beside the packed kernel's budget (two waves up to
+// 121 velocities; one wave beyond 144); at 144 velocities the wall path
+// needs more than two waves allow.
+template <int LX, int LY, int ST>
+constexpr bool merged_walls()
+{
+    return Lat<LX, LY, ST>::Q <= 121 || Lat<LX, LY, ST>::Q > 144;
+}
+
 // Waves per SIMD to ask of the register allocator for the 16-bit kernels: two
 // up to 144 velocities; beyond, two waves would force large spills (the
 // populations of a node do not fit 256 registers beside the collision), so
@@ -877,11 +894,27 @@ constexpr int packed_waves()
 // pairs to their use (hiding load latency) and ends a few registers above the
 // 256 that two waves allow, halving the bytes in flight of a memory-bound
 // kernel.
-template <int LX, int LY, int ST, int BCX, int BCY>
+//
+// WALLS: the same launch also steps the rows next to the walls (FP32
+// registers), in its first blocks (a multiple of 8, so that the interior
+// blocks keep their XCD order): the small, latency-bound wall rows then run
+// beside the interior instead of in a launch of their own after it.
+template <int LX, int LY, int ST, int BCX, int BCY, bool WALLS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(packed_waves<LX, LY, ST>()))) void
 step_kernel_packed(KArgs p)
 {
-    const int i = row_set_node<LY, ROWS_INTERIOR>(tile_index(p) * kBlock + (int)threadIdx.x, p.nx, p.ny);
+    int b = blockIdx.x, G = gridDim.x;
+    if constexpr (WALLS) {
+        const int wb = wall_blocks<LY>(p.nx);
+        if (b < wb) {
+            const int i = row_set_node<LY, ROWS_WALLS>(b * kBlock + (int)threadIdx.x, p.nx, p.ny);
+            if (i >= 0) step_node<LX, LY, ST, BCX, BCY, ROWS_WALLS>(p, i, p.seed);
+            return;
+        }
+        b -= wb;
+        G -= wb;
+    }
+    const int i = row_set_node<LY, ROWS_INTERIOR>(tile_of(b, G, p.remap) * kBlock + (int)threadIdx.x, p.nx, p.ny);
     if (i < 0) return;
     step_node<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>(p, i, p.seed);
 }

@@ -15,14 +15,25 @@ struct Launchers {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
         if constexpr (Elem<ST>::bytes == 2 && BCY == BCY_WALL) {
-            // packed interior rows, then the rows next to the walls
+            // packed interior rows and the rows next to the walls: one launch
+            // where both fit the packed kernel's registers, else two
             constexpr int R = Axis<LY>::vmax;  // rows next to each wall that take emission
             const int interior = (a.ny - 2 * R) * a.nx, walls = 2 * R * a.nx;
-            if (interior > 0)
-                hipLaunchKernelGGL((step_kernel_packed<LX, LY, ST, BCX, BCY>),
-                                   dim3((interior + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
-            hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>), dim3((walls + kBlock - 1) / kBlock),
-                               dim3(kBlock), 0, s, a);
+            const int ib = (interior + kBlock - 1) / kBlock;
+            if constexpr (merged_walls<LX, LY, ST>()) {
+                if (interior > 0)
+                    hipLaunchKernelGGL((step_kernel_packed<LX, LY, ST, BCX, BCY, true>),
+                                       dim3(wall_blocks<LY>(a.nx) + ib), dim3(kBlock), 0, s, a);
+                else
+                    hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>),
+                                       dim3((walls + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+            } else {
+                if (interior > 0)
+                    hipLaunchKernelGGL((step_kernel_packed<LX, LY, ST, BCX, BCY, false>), dim3(ib), dim3(kBlock), 0,
+                                       s, a);
+                hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>),
+                                   dim3((walls + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+            }
         } else {
             hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_ALL>), dim3(grid), dim3(kBlock), 0, s, a);
         }
