@@ -318,40 +318,73 @@ __device__ __forceinline__ void node_xyz(const KArgs &p, int i, int &x, int &y, 
     y = r - z * p.ny;
 }
 
-// One step over a set of rows (StepRows): every row, the rows of each z plane
-// that take no wall emission, or the rows next to the walls (as many as the
-// fastest y velocity reaches), so that the interior pull has no branches.
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY, int ROWS>
-__global__ __launch_bounds__(kBlock) void step3_kernel(KArgs p)
+// Blocks of the wall rows of a 3D step with walls (a multiple of 8).
+template <int LY>
+__host__ __device__ constexpr int wall_blocks3(int nx, int nz)
+{
+    return ((2 * Axis<LY>::vmax * nx * nz + kBlock - 1) / kBlock + 7) / 8 * 8;
+}
+
+// One node (x, y, z) of a step; INTERIOR: no wall emission reaches it.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
+__device__ __forceinline__ void step3_node(const KArgs &p, int x, int y, int z)
 {
     using L = Lat3<LX, LY, LZ, ST>;
-    const int j = tile_index(p) * kBlock + (int)threadIdx.x;
-    int x, y, z;
-    if constexpr (ROWS == ROWS_ALL) {
-        if (j >= p.nodes) return;
-        node_xyz(p, j, x, y, z);
-    } else {
-        constexpr int R = Axis<LY>::vmax;
-        const int rows = ROWS == ROWS_INTERIOR ? p.ny - 2 * R : 2 * R;
-        const int per = rows * p.nx;
-        if (j >= per * p.nz) return;
-        z = j / per;
-        const int r = j - z * per;
-        const int yr = r / p.nx;
-        x = r - yr * p.nx;
-        y = ROWS == ROWS_INTERIOR ? yr + R : (yr < R ? yr : p.ny - 2 * R + yr);
-    }
     const int i = (z * p.ny + y) * p.nx + x;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
     const XAddr<LX, L::EB, BCX> xa(x, p.nx);
     float v[L::QZ][L::QY][L::QX];
-    pull3<LX, LY, LZ, ST, BCX, BCY, ROWS == ROWS_INTERIOR>(p, rs, xa, y, z, v);
+    pull3<LX, LY, LZ, ST, BCX, BCY, INTERIOR>(p, rs, xa, y, z, v);
     float rho, jx, jy, jz;
     moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
     const float inv = 1.0f / rho;
     collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv);
     store3<LX, LY, LZ, ST, BCX>(p, rd, x, z * p.ny + y, v, ST == ST_BF16SR ? node_hash(p.seed, i) : 0u);
+}
+
+// Node of launch index j within a set of rows of every z plane: the rows
+// that take no wall emission, or the rows next to the walls (as many as the
+// fastest y velocity reaches); false outside the set.
+template <int LY, int ROWS>
+__device__ __forceinline__ bool row_set_node3(const KArgs &p, int j, int &x, int &y, int &z)
+{
+    constexpr int R = Axis<LY>::vmax;
+    const int rows = ROWS == ROWS_INTERIOR ? p.ny - 2 * R : 2 * R;
+    const int per = rows * p.nx;
+    if (j >= per * p.nz) return false;
+    z = j / per;
+    const int r = j - z * per;
+    const int yr = r / p.nx;
+    x = r - yr * p.nx;
+    y = ROWS == ROWS_INTERIOR ? yr + R : (yr < R ? yr : p.ny - 2 * R + yr);
+    return true;
+}
+
+// One step.  Periodic y: every node alike.  Walls: one launch whose first
+// blocks (a multiple of 8, so that the others keep their XCD order) step the
+// rows next to the walls and the others the interior rows, whose pull has no
+// branches (all of a node's loads in flight together).
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void step3_kernel(KArgs p)
+{
+    int x, y, z;
+    if constexpr (BCY != BCY_WALL) {
+        const int j = tile_index(p) * kBlock + (int)threadIdx.x;
+        if (j >= p.nodes) return;
+        node_xyz(p, j, x, y, z);
+        step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z);
+    } else {
+        const int wb = wall_blocks3<LY>(p.nx, p.nz);
+        const int b = blockIdx.x;
+        if (b < wb) {
+            if (row_set_node3<LY, ROWS_WALLS>(p, b * kBlock + (int)threadIdx.x, x, y, z))
+                step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z);
+            return;
+        }
+        const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * kBlock + (int)threadIdx.x;
+        if (row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z)) step3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, x, y, z);
+    }
 }
 
 // Moments of f(t) (FP64 sums of the stored values), as observe_kernel.

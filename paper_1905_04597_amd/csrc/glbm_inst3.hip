@@ -13,18 +13,12 @@ struct Launchers3 {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
         if constexpr (BCY == BCY_WALL) {
-            // rows that take no wall emission (branch-free pull), then the
-            // rows next to the walls
+            // the wall rows in the first blocks, then the interior rows
             constexpr int R = Axis<LY>::vmax;
-            const int interior = a.nz * (a.ny - 2 * R) * a.nx, walls = a.nz * 2 * R * a.nx;
-            if (interior > 0)
-                hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY, ROWS_INTERIOR>),
-                                   dim3((interior + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
-            hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY, ROWS_WALLS>),
-                               dim3((walls + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
-        } else {
-            hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY, ROWS_ALL>), dim3(grid), dim3(kBlock), 0, s, a);
+            const int interior = a.nz * (a.ny - 2 * R) * a.nx;
+            grid = wall_blocks3<LY>(a.nx, a.nz) + (interior + kBlock - 1) / kBlock;
         }
+        hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
     static hipError_t observe(const KArgs &a, int grid, hipStream_t s)
