@@ -512,13 +512,15 @@ __device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, const 
 
 // Pre-collision populations of node (x, y) at the new time: pulled from the
 // source buffer, or emitted by a wall where the source row is outside.
-template <int LX, int LY, int ST, int BCX, int BCY>
+// INTERIOR: the node is at least the fastest y velocity away from both walls,
+// so nothing is emitted into it and the pull has no branches.
+template <int LX, int LY, int ST, int BCX, int BCY, bool INTERIOR = false>
 __device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
                                      float (&v)[Axis<LY>::Q][Axis<LX>::Q])
 {
     using L = Lat<LX, LY, ST>;
     float rw[2] = {0.0f, 0.0f};
-    if constexpr (BCY == BCY_WALL) {
+    if constexpr (BCY == BCY_WALL && !INTERIOR) {
         // the mass the FP32 emission tables give out per unit wall density
         constexpr double jp = half_flux_f32<LY>();
         constexpr int reach = Axis<LY>::vmax;  // rows that take wall emission
@@ -531,8 +533,8 @@ __device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, 
         int ys = y - cb;
         bool emit = false;
         if constexpr (BCY == BCY_WALL) {
-            if constexpr (cb > 0) emit = ys < 0;
-            if constexpr (cb < 0) emit = ys >= p.ny;
+            if constexpr (cb > 0 && !INTERIOR) emit = ys < 0;
+            if constexpr (cb < 0 && !INTERIOR) emit = ys >= p.ny;
         } else {
             if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
             if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
@@ -830,7 +832,7 @@ __device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
     } else {
         float v[L::QY][L::QX];
         const XAddr<LX, L::EB, BCX> xa(x, p.nx);
-        pull<LX, LY, ST, BCX, BCY>(p, rs, xa, y, v);
+        pull<LX, LY, ST, BCX, BCY, ROWS == ROWS_INTERIOR>(p, rs, xa, y, v);
         FloatRegs<LX, LY> regs{v};
         float rho, jx, jy, ux, uy;
         density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
@@ -889,19 +891,29 @@ constexpr int packed_waves()
     return Lat<LX, LY, ST>::Q <= 144 ? 2 : 1;
 }
 
-// The packed 16-bit interior rows, asking the register allocator for two
-// waves per SIMD up to 144 velocities: left to itself the scheduler sinks the packing of loaded
-// pairs to their use (hiding load latency) and ends a few registers above the
-// 256 that two waves allow, halving the bytes in flight of a memory-bound
-// kernel.
+// Waves per SIMD asked of the register allocator by the rows kernel: the
+// packed 16-bit budget, no request (one wave at least) for FP32.
+template <int LX, int LY, int ST>
+constexpr int interior_waves()
+{
+    return Elem<ST>::bytes == 2 ? packed_waves<LX, LY, ST>() : 1;
+}
+
+// The interior rows of a lattice with walls (no wall emission reaches them:
+// a pull without branches), in FP32 registers or, with 16-bit storage,
+// packed two per register.  For the packed rows the register allocator is
+// asked for two waves per SIMD up to 144 velocities: left to itself the
+// scheduler sinks the packing of loaded pairs to their use (hiding load
+// latency) and ends a few registers above the 256 that two waves allow,
+// halving the bytes in flight of a memory-bound kernel.
 //
 // WALLS: the same launch also steps the rows next to the walls (FP32
 // registers), in its first blocks (a multiple of 8, so that the interior
 // blocks keep their XCD order): the small, latency-bound wall rows then run
 // beside the interior instead of in a launch of their own after it.
 template <int LX, int LY, int ST, int BCX, int BCY, bool WALLS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(packed_waves<LX, LY, ST>()))) void
-step_kernel_packed(KArgs p)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(interior_waves<LX, LY, ST>()))) void
+step_kernel_rows(KArgs p)
 {
     int b = blockIdx.x, G = gridDim.x;
     if constexpr (WALLS) {
