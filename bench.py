@@ -358,6 +358,7 @@ def main(argv=None):
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-only", action="store_true", help="print only the served-mix record")
     ap.add_argument("--served-seconds", type=float, default=12.0)
+    ap.add_argument("--only-3d", action="store_true", help="print only the three-dimensional sweep lines")
     a = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -372,6 +373,11 @@ def main(argv=None):
     if a.served_only:
         print(json.dumps(run_served(a.served_seconds)), flush=True)
         print(json.dumps(run_solves()), flush=True)
+        return 0
+    if a.only_3d:
+        for levels, ev, shape in (((1, 1, 1), False, (256, 256, 128)), ((2, 2, 2), False, (128, 128, 128)),
+                                  ((1, 3, 1), False, (256, 128, 128)), ((1, 3, 1), True, (256, 128, 128))):
+            print(json.dumps(run_gpu3(levels, ev, *shape, a.storage, a.sweep_steps, 5)), flush=True)
         return 0
     if a.batched_only:
         print(json.dumps(run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)), flush=True)

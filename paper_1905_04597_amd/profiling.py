@@ -127,10 +127,51 @@ def batched_summary(trace: str, command: str, count: int = 512, storage: str = "
     print(path)
 
 
+def three_d_summary(trace: str, command: str, steps: int = 20, storage: str = "f32_shifted"):
+    """Kernel trace of the three-dimensional lattices of the bench sweep:
+    average duration of each lattice's step kernel, and the algorithmic HBM
+    rate 2 Q s nodes / duration."""
+    import re
+
+    eb = 4 if storage.startswith("f32") else 2
+    shapes = {(1, 1, 1): (27, 256 * 256 * 128), (2, 2, 2): (125, 128 ** 3), (1, 3, 1): (63, 256 * 128 * 128),
+              (1, 11, 1): (72, 256 * 128 * 128)}
+    stats = kernel_stats(trace)
+    path = os.path.join(PROFILES, "step3_kernel_3d_sweep_%s.md" % storage)
+    with open(path, "w") as fh:
+        fh.write("# Three-dimensional step kernels, bench sweep shapes (storage %s)\n\n" % storage)
+        fh.write("Command (run on one MI355X):\n\n```\n%s\n```\n\n" % command.strip())
+        fh.write("## rocprofv3 --kernel-trace --stats (top kernels)\n\n| kernel | calls | avg us | total us | % |\n"
+                 "|---|---|---|---|---|\n")
+        for st in stats[:12]:
+            fh.write("| `%s` | %d | %.1f | %.1f | %.2f |\n" % (st["name"][:90], st["calls"], st["avg_us"], st["total_us"],
+                                                           st["pct"]))
+        fh.write("\n## Step kernels\n\n| lattice (axis codes x, y, z) | Q | nodes | avg us | algorithmic GB/s |"
+                 "\n|---|---|---|---|---|\n")
+        for st in stats:
+            m = re.search(r"step3_kernel<(\d+), (\d+), (\d+),", st["name"])
+            if not m:
+                continue
+            key = tuple(int(g) for g in m.groups())
+            if key not in shapes:
+                continue
+            q, nodes = shapes[key]
+            fh.write("| %s | %d | %d | %.1f | %.0f |\n" % (key, q, nodes, st["avg_us"],
+                                                        2 * q * eb * nodes / (st["avg_us"] * 1e-6) / 1e9))
+    print(path)
+
+
 def main(argv=None):
     import sys
 
     argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "three_d":
+        tp = argparse.ArgumentParser()
+        tp.add_argument("--trace", required=True)
+        tp.add_argument("--command", required=True)
+        tp.add_argument("--storage", default="f32_shifted")
+        t = tp.parse_args(argv[1:])
+        return three_d_summary(t.trace, t.command, storage=t.storage)
     if argv and argv[0] == "batched":
         bp = argparse.ArgumentParser()
         bp.add_argument("--trace", required=True)
