@@ -546,14 +546,17 @@ static void kadd(ksum *k, double v)
  *  out[8] x momentum given to the top wall
  *  out[9] number of nodes outside the positivity domain of section 3 on
  *         any axis (see axis_setup)
- *  out[10] momentum z  sum f(t) c_z */
+ *  out[10] momentum z  sum f(t) c_z
+ *  out[11] number of nodes whose density, momentum or energy is not a
+ *          finite number (failure detection; such a node is not counted in
+ *          out[9], and it makes the sums above non-finite) */
 void orc_stats(orc_solver *s, double *out)
 {
     const int64_t n = nodes(s), ncol = s->nx * s->nz;
     ksum m = {0, 0}, px = {0, 0}, py = {0, 0}, pz = {0, 0}, e = {0, 0}, d2 = {0, 0}, u2 = {0, 0};
     double *ux = (double *)malloc(sizeof(double) * (size_t)n);
     collide_all(s, s->f, s->fs, ux);
-    double npos = 0;
+    double npos = 0, nbad = 0;
     for (int64_t k = 0; k < n; ++k) {
         double r = 0, jx = 0, jy = 0, jz = 0, en = 0;
         for (int c = 0; c < s->Qz; ++c)
@@ -569,7 +572,9 @@ void orc_stats(orc_solver *s, double *out)
         kadd(&u2, ux[k] * ux[k]);
         kadd(&d2, (ux[k] - s->ux_prev[k]) * (ux[k] - s->ux_prev[k]));
         const double vy = jy / r, vz = jz / r;
-        if (ux[k] * ux[k] > s->u2x || (s->dims >= 2 && vy * vy > s->u2y) || (s->dims == 3 && vz * vz > s->u2z))
+        if (!isfinite(r) || !isfinite(jx) || !isfinite(jy) || !isfinite(jz) || !isfinite(en))
+            nbad += 1;
+        else if (ux[k] * ux[k] > s->u2x || (s->dims >= 2 && vy * vy > s->u2y) || (s->dims == 3 && vz * vz > s->u2z))
             npos += 1;
     }
     out[0] = m.s; out[1] = px.s; out[2] = py.s; out[3] = e.s;
@@ -595,5 +600,6 @@ void orc_stats(orc_solver *s, double *out)
     }
     out[9] = npos;
     out[10] = pz.s;
+    out[11] = nbad;
     free(ux);
 }

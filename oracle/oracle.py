@@ -160,7 +160,7 @@ class OracleSolver:
     STAT_NAMES = (
         "mass", "momentum_x", "momentum_y", "energy_post", "residual",
         "wall_mass_bottom", "wall_mass_top", "wall_momentum_bottom", "wall_momentum_top",
-        "nonpositive_nodes", "momentum_z",
+        "nonpositive_nodes", "momentum_z", "nonfinite_nodes",
     )
 
     def __init__(self, dims, level_x, level_y=0, nx=1, ny=1, tau=0.0, kn=0.0,
