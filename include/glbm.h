@@ -51,6 +51,10 @@ extern "C" {
 #define GLBM_ERR_UNSUPPORTED (-2) /* valid but not built (level, storage, boundary combination) */
 #define GLBM_ERR_HIP (-3)         /* a HIP runtime call failed */
 #define GLBM_ERR_STATE (-4)       /* call out of order (e.g. step before init) */
+#define GLBM_ERR_NONFINITE (-5)   /* glbm_stats: some node's density, momentum or energy is not a
+                                     finite number (the run has blown up) */
+#define GLBM_ERR_POSITIVITY (-6)  /* glbm_stats: some node's velocity is outside the domain in
+                                     which the equilibrium is non-negative (section 3) */
 
 /* Boundary kinds. */
 #define GLBM_BC_PERIODIC 0
@@ -60,8 +64,14 @@ extern "C" {
 /* Population storage. */
 #define GLBM_STORE_F32 0          /* f in FP32 */
 #define GLBM_STORE_F32_SHIFTED 1  /* f - S in FP32: S is the rest state W_a W_b rounded to
-                                     multiples of 2^-24 with unit sum (deviation storage) */
-#define GLBM_STORE_BF16_SHIFTED 2 /* f - S in BF16, round to nearest even */
+                                     multiples of 2^-24 with unit sum (deviation storage); the
+                                     relaxation update is rounded without bias (dithered by
+                                     one unit in the last place, random bits keyed by (time
+                                     step, node, velocity): reproducible) */
+#define GLBM_STORE_BF16_SHIFTED 2 /* f - S in BF16, round to nearest even.  Undriven lattices
+                                     only (no force, no walls): per-step increments below half
+                                     a BF16 unit are lost, so a driven flow stalls; creation
+                                     with a force or walls returns GLBM_ERR_UNSUPPORTED */
 #define GLBM_STORE_BF16_SHIFTED_SR 3 /* f - S in BF16, stochastic rounding keyed by
                                         (time step, node, velocity): reproducible */
 
@@ -122,6 +132,9 @@ typedef struct glbm_stats {
                                  underlying 2N+1 walk: N/3, or 4N/3 on an even axis's half grid)
                                  (equilibrium not positive, section 3) */
     double momentum_z;      /* sum of f(t) c_z (three dimensions; 0 otherwise) */
+    double nonfinite_nodes; /* nodes whose density, momentum or energy is not a finite number
+                               (not counted in nonpositive_nodes; they make the sums above
+                               non-finite) */
 } glbm_stats_t;
 
 typedef struct glbm_solver glbm_t;
@@ -135,13 +148,24 @@ typedef struct glbm_solver glbm_t;
  * the whole device footprint apart from a few KB of tables). */
 size_t glbm_population_bytes(const glbm_config *cfg);
 
+/* Device bytes a solver of cfg occupies in total: its two population buffers
+ * (caller-owned) plus the FP64 statistics buffers the library allocates on
+ * the first glbm_stats call (a fixed number of partial-sum rows, at most
+ * 2048 x 13 doubles); 0 if cfg is invalid.  For HBM-budget admission. */
+size_t glbm_required_bytes(const glbm_config *cfg);
+
 /* Create a solver over caller-owned device buffers pop_a and pop_b, each of
  * glbm_population_bytes(cfg) bytes, 256-byte aligned, on HIP stream `stream`
- * (hipStream_t; NULL = the default stream).  The state is undefined until
- * glbm_init_fields or glbm_init_populations.  *out receives the handle.
+ * (hipStream_t; NULL = the default stream).  The relaxation time is cfg->tau,
+ * or, with tau <= 0, the one Eq. kn gives for cfg->kn (kinematic viscosity
+ * nu = theta tau, section 5.2: tau = Kn H / sqrt(2 theta)); the collision
+ * frequency of Eq. maineq01 is 1 / (tau + 1/2).  The state is undefined until
+ * glbm_init_fields or glbm_init_populations.  *out receives the handle; the
+ * caller keeps the buffers alive until glbm_destroy.
  * Errors: GLBM_ERR_INVALID for a bad configuration (including omega outside
  * (0, 2), ny < 2 Ny with walls, walls combined with equilibrium ends, a
- * buffer above 4 GiB), GLBM_ERR_UNSUPPORTED for level combinations not built. */
+ * buffer above 4 GiB), GLBM_ERR_UNSUPPORTED for level combinations not built
+ * and for round-to-nearest BF16 storage with a force or walls. */
 int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, glbm_t **out);
 
 /* f(0) = f^eq(rho, u) at every node (Eqs. maineq02-maineq06 per axis, product
@@ -157,10 +181,12 @@ int glbm_init_populations(glbm_t *h, const float *f0);
  * with force, wall densities, pull streaming; one fused kernel per step). */
 int glbm_step(glbm_t *h, int64_t nsteps);
 
-/* Moments of f(t): density, velocity, temperature per degree of freedom
- * T = (sum f |c|^2 / rho - |u|^2) / dims and shear moment
- * Pxy = sum f c_x c_y - rho u_x u_y.  Device float arrays [ny][nx]; any may
- * be NULL (skipped). */
+/* Moments of f(t) (the hydrodynamic moments of section 2: density sum f,
+ * momentum sum f c, and the second moments): density, velocity u = sum f c /
+ * rho, temperature per degree of freedom T = (sum f |c|^2 / rho - |u|^2) /
+ * dims and shear moment Pxy = sum f c_x c_y - rho u_x u_y, summed in FP64 and
+ * rounded to FP32.  Device float arrays [ny][nx]; any may be NULL (skipped).
+ * Asynchronous on the solver's stream. */
 int glbm_moments(glbm_t *h, float *rho, float *ux, float *uy, float *T, float *pxy);
 
 /* As glbm_init_fields, with the z velocity uz (three dimensions; may be NULL).
@@ -177,7 +203,12 @@ int glbm_moments3(glbm_t *h, float *rho, float *ux, float *uy, float *uz, float 
 int glbm_get_populations(glbm_t *h, float *out);
 
 /* Global FP64 diagnostics at the current time.  Synchronizes the stream.  The
- * first call allocates the solver's small FP64 reduction buffers. */
+ * first call allocates the solver's small FP64 reduction buffers.  *out is
+ * filled in every case where the sums were read; the status then reports the
+ * state's health: GLBM_ERR_NONFINITE if some node is not finite (the run has
+ * blown up), else GLBM_ERR_POSITIVITY if some node's velocity is outside the
+ * positivity domain of section 3 (|u| <= sqrt(2 N theta0) per axis), else
+ * GLBM_OK. */
 int glbm_stats(glbm_t *h, glbm_stats_t *out);
 
 /* Derived parameters: relaxation time, collision frequency 1/(tau + 1/2),
@@ -251,6 +282,18 @@ int glbm_batch_update(glbm_batch_t *b, glbm_t *const *members, int32_t n);
 /* Release the batch (members stay valid and can be stepped alone again).
  * Waits for the batch's work. */
 int glbm_batch_destroy(glbm_batch_t *b);
+
+/* ------------------------------------------------------------------------
+ * Measurement utility (not part of the method): the HBM rates of plain
+ * streaming kernels on this GPU, the ceiling against which the step kernels'
+ * bandwidth fractions are read, and a kernel of known byte count for
+ * calibrating memory counters.  mode 0 copies `bytes` from src to dst, mode 1
+ * reads src (dst: a 4-byte device word that is almost never written), mode 2
+ * writes dst; 16-byte non-temporal accesses in grid-stride loops over
+ * `blocks` workgroups of 256 lanes, enqueued on `stream`.  bytes must be a
+ * positive multiple of 16 and the buffers 16-byte aligned device memory of
+ * the caller; GLBM_ERR_INVALID otherwise. */
+int glbm_bandwidth_probe(int32_t mode, const void *src, void *dst, size_t bytes, int32_t blocks, void *stream);
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,8 @@ def _hipcc() -> str:
 
 def _deps(src: str):
     common = [os.path.join(CSRC, f) for f in ("glbm_device.h", "glbm_internal.h", "glbm_device3.h")]
+    if src.endswith("glbm_probe.hip"):
+        return [src, os.path.join(os.path.dirname(HERE), "include", "glbm.h")]
     if src.endswith("glbm_api.hip"):
         common.append(os.path.join(os.path.dirname(HERE), "include", "glbm.h"))
     return [src] + common
@@ -65,6 +67,7 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
     # the three-dimensional objects are among the slowest: start them first
     tasks = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3.o"), [])]
     tasks.append((os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), []))
+    tasks.append((os.path.join(CSRC, "glbm_probe.hip"), os.path.join(BUILD, "glbm_probe.o"), []))
     for lv in LEVELS:
         for even in (0, 1):
             for compact in (0, 1):

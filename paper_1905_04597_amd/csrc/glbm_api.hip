@@ -153,6 +153,13 @@ int check_config(const glbm_config *c, Geometry *g)
                     ay.vmax);
     if (c->bc_x == GLBM_BC_EQ_ENDS && nx < ax.vmax)
         return fail(GLBM_ERR_INVALID, "nx must be at least the fastest x velocity with equilibrium ends");
+    // round to nearest loses every per-step increment below half a BF16 unit
+    // of the deviation: a driven flow (force or walls) stalls far from the
+    // solution, so the storage is offered for undriven lattices only
+    if (c->storage == GLBM_STORE_BF16_SHIFTED && (c->g != 0.0 || bcy == GLBM_BC_WALL))
+        return fail(GLBM_ERR_UNSUPPORTED,
+                    "round-to-nearest BF16 storage stalls driven flows (force or walls): use the stochastic "
+                    "rounding storage");
     g->x = ax;
     g->y = ay;
     g->z = az;
@@ -235,6 +242,26 @@ size_t glbm_population_bytes(const glbm_config *cfg)
     Geometry g;
     if (check_config(cfg, &g) != GLBM_OK) return 0;
     return (size_t)g.buf_bytes;
+}
+
+// Rows of FP64 partial sums of one statistics launch (the blocks stride over
+// the nodes), and the bytes of a solver's statistics buffers.
+static int stat_blocks(int64_t nodes)
+{
+    const int64_t g = (nodes + kBlock - 1) / kBlock;
+    return (int)std::min<int64_t>(g, kStatBlocks);
+}
+
+static size_t stats_bytes(int64_t nodes)
+{
+    return sizeof(double) * kNumStats * ((size_t)stat_blocks(nodes) + 1);
+}
+
+size_t glbm_required_bytes(const glbm_config *cfg)
+{
+    Geometry g;
+    if (check_config(cfg, &g) != GLBM_OK) return 0;
+    return 2 * (size_t)g.buf_bytes + stats_bytes(g.nx * g.ny * g.nz);
 }
 
 int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, glbm_t **out)
@@ -418,37 +445,25 @@ int glbm_get_populations(glbm_t *h, float *out)
     return observe(h, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, out);
 }
 
-int glbm_stats(glbm_t *h, glbm_stats_t *out)
+// Statistics of h into *out through the FP64 buffers partials (stat_blocks
+// rows) and dout (kNumStats values) on the device and hout on the host;
+// synchronizes the stream.  Returns the failure status of the state.
+static int stats_through(glbm_t *h, double *partials, double *dout, double *hout, glbm_stats_t *out)
 {
-    if (!h || !out) return fail(GLBM_ERR_INVALID, "NULL argument");
-    if (!h->ready) return fail(GLBM_ERR_STATE, "stats before init");
-    hipError_t e = hipSuccess;
-    if (!h->d_partials) {
-        e = hipMalloc((void **)&h->d_partials, sizeof(double) * kNumStats * (size_t)h->grid);
-        if (e == hipSuccess) e = hipMalloc((void **)&h->d_out, sizeof(double) * kNumStats);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_out, sizeof(double) * kNumStats, hipHostMallocDefault);
-        if (e != hipSuccess) {
-            (void)hipFree(h->d_partials);
-            (void)hipFree(h->d_out);
-            h->d_partials = nullptr;
-            h->d_out = nullptr;
-            h->h_out = nullptr;
-            return hip_fail(e, "allocating statistics buffers");
-        }
-    }
     KArgs a = h->base;
     a.src = h->buf[h->cur];
     a.prev = h->t > 0 ? h->buf[1 - h->cur] : nullptr;
-    a.partials = h->d_partials;
-    e = h->var->stats(a, h->grid, h->stream);
+    a.partials = partials;
+    const int blocks = stat_blocks((int64_t)a.nodes);
+    hipError_t e = h->var->stats(a, blocks, h->stream);
     if (e != hipSuccess) return hip_fail(e, "launching the stats kernel");
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kBlock), 0, h->stream, h->d_partials, h->grid, h->d_out);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kBlock), 0, h->stream, partials, blocks, dout);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "launching the reduction");
-    e = hipMemcpyAsync(h->h_out, h->d_out, sizeof(double) * kNumStats, hipMemcpyDeviceToHost, h->stream);
+    e = hipMemcpyAsync(hout, dout, sizeof(double) * kNumStats, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "reading the statistics");
-    const double *s = h->h_out;
+    const double *s = hout;
     out->time = h->t;
     out->mass = s[0];
     out->momentum_x = s[1];
@@ -461,7 +476,36 @@ int glbm_stats(glbm_t *h, glbm_stats_t *out)
     out->wall_momentum[1] = s[9];
     out->nonpositive_nodes = s[10];
     out->momentum_z = s[11];
+    out->nonfinite_nodes = s[12];
+    if (s[12] > 0)
+        return fail(GLBM_ERR_NONFINITE, "%.0f nodes have a non-finite density, momentum or energy at t = %lld", s[12],
+                    (long long)h->t);
+    if (s[10] > 0)
+        return fail(GLBM_ERR_POSITIVITY, "%.0f nodes are outside the positivity domain of the equilibrium at t = %lld",
+                    s[10], (long long)h->t);
     return GLBM_OK;
+}
+
+int glbm_stats(glbm_t *h, glbm_stats_t *out)
+{
+    if (!h || !out) return fail(GLBM_ERR_INVALID, "NULL argument");
+    if (!h->ready) return fail(GLBM_ERR_STATE, "stats before init");
+    hipError_t e = hipSuccess;
+    if (!h->d_partials) {
+        const size_t rows = (size_t)stat_blocks((int64_t)h->base.nodes);
+        e = hipMalloc((void **)&h->d_partials, sizeof(double) * kNumStats * rows);
+        if (e == hipSuccess) e = hipMalloc((void **)&h->d_out, sizeof(double) * kNumStats);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->h_out, sizeof(double) * kNumStats, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipFree(h->d_partials);
+            (void)hipFree(h->d_out);
+            h->d_partials = nullptr;
+            h->d_out = nullptr;
+            h->h_out = nullptr;
+            return hip_fail(e, "allocating statistics buffers");
+        }
+    }
+    return stats_through(h, h->d_partials, h->d_out, h->h_out, out);
 }
 
 int glbm_info(const glbm_t *h, double *tau, double *omega, int32_t *nvel, int64_t *time)

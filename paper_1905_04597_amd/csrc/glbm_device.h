@@ -43,7 +43,7 @@ namespace glbm {
 constexpr int kMaxLevel = 7;
 constexpr int kMaxQ1 = 2 * kMaxLevel + 2;  // velocities of the largest axis
 constexpr int kBlock = 256;
-constexpr int kNumStats = 12;
+constexpr int kNumStats = 13;
 constexpr int kGhost = 64;  // padded column of node x = 0 (>= the largest level)
 
 enum StorageKind { ST_F32 = 0, ST_F32S = 1, ST_BF16S = 2, ST_BF16SR = 3 };
@@ -628,6 +628,43 @@ __device__ __forceinline__ void density_velocity(const Regs &v, float &rho, floa
     uy = jy * inv;
 }
 
+// Storages whose update draws random bits: stochastic rounding of the BF16
+// stores, and the dithered FP32 update below.
+template <int ST>
+constexpr bool draws_bits()
+{
+    return ST == ST_BF16SR || ST == ST_F32S;
+}
+
+// f + omega neq + force, rounded once.  FP32 deviation storage rounds the sum
+// without bias: a dither uniform over one unit in the last place of the sum
+// (from the exponent of the sum rounded to nearest, and 32 random bits) is
+// added to the increment, so that the rounding to nearest of f + increment +
+// dither rounds f + increment up or down with the probabilities of its
+// position between the two neighbours.  Without it, increments below half a
+// unit of f are lost every step, and at a small collision frequency the
+// steady state sits about eps |f| / (2 omega) from the exact one.  (The
+// dither's scale is taken from the sum, which the collision produces late,
+// rather than from f: formed from f, the scheduler computed all Q dithers
+// next to the loads and ran out of registers.)  Other storages: plain fused
+// multiply-adds.  The force enters as gk * w (its shape per axis).
+template <int ST, int q>
+__device__ __forceinline__ float relax_update(float f, float om, float neq, float gk, float w, uint32_t h)
+{
+    if constexpr (ST == ST_F32S) {
+        const float inc = __builtin_fmaf(om, neq, gk * w);
+        const int e = __builtin_amdgcn_frexp_expf(f + inc);  // f + inc = m 2^e, 1/2 <= |m| < 1
+        // the population's random word from the node's, mixed with the
+        // increment's bits before the rotation: still uniform, and nothing of
+        // it can be formed before the collision
+        const uint32_t rnd = rnd_of<q>(h ^ __builtin_bit_cast(uint32_t, inc));
+        const float d = __builtin_ldexpf((float)(int32_t)rnd, e - 56);  // uniform in [-ulp/2, ulp/2)
+        return f + (inc + d);
+    } else {
+        return __builtin_fmaf(gk, w, __builtin_fmaf(om, neq, f));
+    }
+}
+
 // BGK collision with the linear force, in place on working values:
 // f* = f + omega (rho F_a(u_x) F_b(u_y) - f) + W_a W_b c_a g / theta_x.
 // The relaxation is written as f + omega (f^eq - f) so that no rounded
@@ -640,7 +677,8 @@ __device__ __forceinline__ void density_velocity(const Regs &v, float &rho, floa
 // smallest |c| on axes without one) and of the c = +-1 populations among them
 // (momentum).
 template <int LX, int LY, int ST, class Regs>
-__device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, float jx, float jy, float ux, float uy)
+__device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, float jx, float jy, float ux, float uy,
+                                        uint32_t h)
 {
     using L = Lat<LX, LY, ST>;
     // per-axis equilibrium in FP64 (the FP64 FMA rate equals the unpacked FP32
@@ -694,7 +732,7 @@ __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, floa
             if constexpr (ymin && ca == -1) neq += hx;
             if constexpr (xmin && cb == 1) neq -= hy;
             if constexpr (xmin && cb == -1) neq += hy;
-            v.template put<b, a>(__builtin_fmaf(gK[a], (float)kRest<LY>.w[b], __builtin_fmaf(om, neq, f)));
+            v.template put<b, a>(relax_update<ST, b * L::QX + a>(f, om, neq, gK[a], (float)kRest<LY>.w[b], h));
         });
     });
 }
@@ -731,6 +769,18 @@ __device__ __forceinline__ void store_node(const KArgs &p, rsrc_t rd, int x, int
 __device__ __forceinline__ uint32_t node_hash(uint32_t seed, int i)
 {
     return mix32((uint32_t)i ^ seed);
+}
+
+// Random bits of a node for its storage: BF16 stochastic rounding keys them
+// by the node index; the FP32 dither by the row y alone (the same across x and
+// z), so that a lattice uniform across x (and z) stays bitwise uniform, as it
+// does without random bits.
+template <int ST>
+__device__ __forceinline__ uint32_t storage_hash(uint32_t seed, int i, int y)
+{
+    if constexpr (ST == ST_BF16SR) return node_hash(seed, i);
+    if constexpr (ST == ST_F32S) return node_hash(seed, y);
+    return 0u;
 }
 
 // Seed of the stochastic rounding for the step that produces time t (host and
@@ -792,7 +842,7 @@ __device__ __forceinline__ void step_packed(const KArgs &p, rsrc_t rs, rsrc_t rd
     // the kernel into spills or accumulation registers (2.3-3.1x slower at 196
     // and 225 velocities).  Round to nearest is faster left alone.
     if constexpr (ST == ST_BF16SR) opaque_words(pk);
-    collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
+    collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy, h);
     constexpr int V = Axis<LX>::vmax;
     int pc = x + kGhost;
     if constexpr (BCX == BCX_WRAP) pc = x;
@@ -826,7 +876,7 @@ __device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
     const int y = i / p.nx, x = i - y * p.nx;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
-    const uint32_t h = ST == ST_BF16SR ? node_hash(seed, i) : 0u;
+    const uint32_t h = storage_hash<ST>(seed, i, y);
     if constexpr (L::EB == 2 && ROWS == ROWS_INTERIOR) {
         step_packed<LX, LY, ST, BCX, BCY>(p, rs, rd, x, y, h);
     } else {
@@ -836,7 +886,7 @@ __device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
         FloatRegs<LX, LY> regs{v};
         float rho, jx, jy, ux, uy;
         density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
-        collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
+        collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy, mix32(h));
         store_node<LX, LY, ST, BCX>(p, rd, x, y, v, h);
     }
 }
@@ -856,8 +906,22 @@ __device__ __forceinline__ int row_set_node(int i, int nx, int ny)
     }
 }
 
+// Waves per SIMD asked of the register allocator by the single-lattice step
+// kernel: two for FP32 storages up to 121 velocities, which fit 256
+// registers without spills (left alone, the allocator took 256 registers and
+// accumulation registers for the dithered update at 121 velocities: one wave
+// per SIMD, 18% slower); no request beyond, or for the 16-bit wall-row
+// launches.  (The same request spilled in the resident and three-dimensional
+// kernels, which are left alone.)
+template <int LX, int LY, int ST>
+constexpr int step_waves()
+{
+    return Elem<ST>::bytes == 4 && Lat<LX, LY, ST>::Q <= 121 ? 2 : 1;
+}
+
 template <int LX, int LY, int ST, int BCX, int BCY, int ROWS>
-__global__ __launch_bounds__(kBlock) void step_kernel(KArgs p)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves<LX, LY, ST>()))) void
+step_kernel(KArgs p)
 {
     const int i = row_set_node<LY, ROWS>(tile_index(p) * kBlock + (int)threadIdx.x, p.nx, p.ny);
     if (i < 0) return;
@@ -892,11 +956,13 @@ constexpr int packed_waves()
 }
 
 // Waves per SIMD asked of the register allocator by the rows kernel: the
-// packed 16-bit budget, no request (one wave at least) for FP32.
+// packed 16-bit budget; two for FP32 up to 121 velocities (the dithered
+// update took the G-D2Q(12x12) rows kernel to one wave otherwise; at 144
+// velocities two waves spill), none beyond.
 template <int LX, int LY, int ST>
 constexpr int interior_waves()
 {
-    return Elem<ST>::bytes == 2 ? packed_waves<LX, LY, ST>() : 1;
+    return Elem<ST>::bytes == 2 ? packed_waves<LX, LY, ST>() : (Lat<LX, LY, ST>::Q <= 121 ? 2 : 1);
 }
 
 // The interior rows of a lattice with walls (no wall emission reaches them:
@@ -956,7 +1022,7 @@ __global__ __launch_bounds__(kBlock) void batch_step_kernel(const BatchTile *__r
     const KArgs &p = args[2 * t.member + (phase[t.member] ^ (int)(s & 1))];
     const int i = row_set_node<LY, ROWS>(t.first + (int)threadIdx.x, p.nx, p.ny);
     if (i < 0) return;
-    step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, ST == ST_BF16SR ? step_seed(t0[t.member] + s + 1) : 0u);
+    step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, draws_bits<ST>() ? step_seed(t0[t.member] + s + 1) : 0u);
 }
 
 // Resident batched steps for small lattices: block b owns member
@@ -983,7 +1049,7 @@ __global__ __launch_bounds__(kBlock) void resident_step_kernel(const int32_t *__
     for (int l = 0; l < steps; ++l) {
         const int64_t s = s0 + l;
         const KArgs &p = args[2 * m + (ph ^ (int)(s & 1))];
-        const uint32_t seed = ST == ST_BF16SR ? step_seed(tm + s + 1) : 0u;
+        const uint32_t seed = draws_bits<ST>() ? step_seed(tm + s + 1) : 0u;
         if constexpr (split) {
             constexpr int R = Axis<LY>::vmax;
             const int interior = (p.ny - 2 * R) * p.nx, walls = 2 * R * p.nx;
@@ -1110,7 +1176,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(KArgs p)
             });
         });
     }
-    const uint32_t h = ST == ST_BF16SR ? node_hash(p.seed, i) : 0u;
+    const uint32_t h = storage_hash<ST>(p.seed, i, y);
     if constexpr (Elem<ST>::bytes == 2) {
         // round f(0) as the storage will, so that f*(0) is the collision of the
         // stored f(0) (the stores below are then exact)
@@ -1126,7 +1192,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(KArgs p)
     FloatRegs<LX, LY> regs{v};
     float rho, jx, jy, ux, uy;
     density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
-    collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy);
+    collide<LX, LY, ST>(p, regs, rho, jx, jy, ux, uy, mix32(mix32(h)));
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
     store_node<LX, LY, ST, BCX>(p, rd, x, y, v, mix32(h));
 }
@@ -1171,18 +1237,51 @@ __global__ __launch_bounds__(kBlock) void ends_kernel(KArgs p, float rho_left, f
 // Global FP64 sums (glbm_stats): per-block partials.
 // [0] mass  [1] momentum x  [2] momentum y  [3] energy (post)  [4] sum u_x^2
 // [5] sum (u_x(t) - u_x(t-1))^2  [6] bottom absorbed mass  [7] bottom x momentum
-// [8] top absorbed mass  [9] top x momentum  [10] non-positive nodes
-// [11] momentum z (three dimensions)
+// [8] top absorbed mass  [9] top x momentum  [10] nodes outside the positivity
+// domain  [11] momentum z (three dimensions)  [12] non-finite nodes
+// The blocks stride over the nodes, so that a launch of at most kStatBlocks
+// blocks covers any lattice and the partials stay a fixed, small array.
+constexpr int kStatBlocks = 2048;
+
+// Failure detection on a node's sums: a density, momentum or energy that is
+// not a finite number marks a node that has blown up (it is then not tested
+// against the positivity domain).
+__device__ __forceinline__ bool finite_node(double r, double jx, double jy, double jz, double e)
+{
+    return __builtin_isfinite(r) && __builtin_isfinite(jx) && __builtin_isfinite(jy) && __builtin_isfinite(jz) &&
+           __builtin_isfinite(e);
+}
+
+// Wave reduction of the per-lane sums, then across the block's waves through
+// LDS; thread k < kNumStats writes the block's partial k.
+__device__ __forceinline__ void write_partials(double (&acc)[kNumStats], double *partials)
+{
+    __shared__ double red[kBlock / 64][kNumStats];
+    for (int k = 0; k < kNumStats; ++k) {
+        double s = acc[k];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        acc[k] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < kNumStats; ++k) red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < kNumStats) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * kNumStats + threadIdx.x] = s;
+    }
+}
+
 template <int LX, int LY, int ST, int BCX, int BCY>
 __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
 {
     using L = Lat<LX, LY, ST>;
-    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
     double acc[kNumStats];
     for (int k = 0; k < kNumStats; ++k) acc[k] = 0.0;
-    if (i < p.nodes) {
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    for (int i = blockIdx.x * kBlock + (int)threadIdx.x; i < p.nodes; i += gridDim.x * kBlock) {
         const int y = i / p.nx, x = i - y * p.nx;
-        const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
         const XAddr<LX, L::EB, BCX> xa(x, p.nx);
         const uint32_t base = xa.own(row_bytes<L::EB>(p, y));
         double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
@@ -1203,11 +1302,11 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
         // f*(t) carries the force momentum g of step t's collision
         const double jx_pre = jx - p.g;
         const double ux = jx_pre / r, uy = jy / r;
-        acc[0] = r;
-        acc[1] = jx_pre;
-        acc[2] = jy;
-        acc[3] = e;
-        acc[4] = ux * ux;
+        acc[0] += r;
+        acc[1] += jx_pre;
+        acc[2] += jy;
+        acc[3] += e;
+        acc[4] += ux * ux;
         if (p.prev) {
             const rsrc_t rp = make_rsrc(p.prev, p.buf_bytes);
             double r0 = 0.0, j0 = 0.0;
@@ -1221,41 +1320,28 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(KArgs p)
             });
             if constexpr (L::shifted) r0 += (double)kShift<LX, LY>.sum;
             const double d = ux - (j0 - p.g) / r0;
-            acc[5] = d * d;
+            acc[5] += d * d;
         }
-        // positivity domain of section 3 (Axis::u2max)
-        if (ux * ux > Axis<LX>::u2max || (LY > 0 && uy * uy > Axis<LY>::u2max)) acc[10] = 1.0;
+        if (!finite_node(r, jx, jy, 0.0, e))
+            acc[12] += 1.0;
+        else if (ux * ux > Axis<LX>::u2max || (LY > 0 && uy * uy > Axis<LY>::u2max))  // section 3 (Axis::u2max)
+            acc[10] += 1.0;
         if constexpr (BCY == BCY_WALL) {
             if (y == 0) {
                 float m;
                 const float A = wall_absorbed<LX, LY, ST, BCX, true>(p, rs, xa, &m);
-                acc[6] = A;
-                acc[7] = (double)m - (double)A * p.uw[0];
+                acc[6] += A;
+                acc[7] += (double)m - (double)A * p.uw[0];
             }
             if (y == p.ny - 1) {
                 float m;
                 const float A = wall_absorbed<LX, LY, ST, BCX, false>(p, rs, xa, &m);
-                acc[8] = A;
-                acc[9] = (double)m - (double)A * p.uw[1];
+                acc[8] += A;
+                acc[9] += (double)m - (double)A * p.uw[1];
             }
         }
     }
-    // wave reduction, then across the block's waves through LDS
-    __shared__ double red[kBlock / 64][kNumStats];
-    for (int k = 0; k < kNumStats; ++k) {
-        double s = acc[k];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        acc[k] = s;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0)
-        for (int k = 0; k < kNumStats; ++k) red[wave][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x < kNumStats) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-        p.partials[(size_t)blockIdx.x * kNumStats + threadIdx.x] = s;
-    }
+    write_partials(acc, p.partials);
 }
 
 }  // namespace glbm

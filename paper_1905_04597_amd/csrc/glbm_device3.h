@@ -190,7 +190,7 @@ __device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX,
 // populations take out.
 template <int LX, int LY, int LZ, int ST>
 __device__ __forceinline__ void collide3(const KArgs &p, float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q], float rho,
-                                         float jx, float jy, float jz, float ux, float uy, float uz)
+                                         float jx, float jy, float jz, float ux, float uy, float uz, uint32_t h)
 {
     using L = Lat3<LX, LY, LZ, ST>;
     const float om = p.omega;
@@ -249,7 +249,7 @@ __device__ __forceinline__ void collide3(const KArgs &p, float (&v)[Axis<LZ>::Q]
                 if constexpr (xmin && zmin && cb == -1) neq += hy;
                 if constexpr (xmin && ymin && cc == 1) neq -= hz;
                 if constexpr (xmin && ymin && cc == -1) neq += hz;
-                v[c][b][a] = __builtin_fmaf(gK[a], kYZ<LY, LZ>.w[c][b], __builtin_fmaf(om, neq, f));
+                v[c][b][a] = relax_update<ST, L::template q<a, b, c>()>(f, om, neq, gK[a], kYZ<LY, LZ>.w[c][b], h);
             });
         });
     });
@@ -339,8 +339,9 @@ __device__ __forceinline__ void step3_node(const KArgs &p, int x, int y, int z)
     float rho, jx, jy, jz;
     moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
     const float inv = 1.0f / rho;
-    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv);
-    store3<LX, LY, LZ, ST, BCX>(p, rd, x, z * p.ny + y, v, ST == ST_BF16SR ? node_hash(p.seed, i) : 0u);
+    const uint32_t h = storage_hash<ST>(p.seed, i, y);
+    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv, mix32(h));
+    store3<LX, LY, LZ, ST, BCX>(p, rd, x, z * p.ny + y, v, h);
 }
 
 // Node of launch index j within a set of rows of every z plane: the rows
@@ -365,8 +366,12 @@ __device__ __forceinline__ bool row_set_node3(const KArgs &p, int j, int &x, int
 // blocks (a multiple of 8, so that the others keep their XCD order) step the
 // rows next to the walls and the others the interior rows, whose pull has no
 // branches (all of a node's loads in flight together).
+// Two waves per SIMD asked of the register allocator up to 125 velocities
+// (G-D3Q125 fits 256 registers without spills; left alone, the dithered FP32
+// update took it to one wave).
 template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
-__global__ __launch_bounds__(kBlock) void step3_kernel(KArgs p)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Lat3<LX, LY, LZ, ST>::Q <= 125 ? 2 : 1))) void
+step3_kernel(KArgs p)
 {
     int x, y, z;
     if constexpr (BCY != BCY_WALL) {
@@ -498,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void init3_kernel(KArgs p)
             });
         });
     }
-    const uint32_t h = ST == ST_BF16SR ? node_hash(p.seed, i) : 0u;
+    const uint32_t h = storage_hash<ST>(p.seed, i, y);
     unroll<L::QZ>([&](auto C) {
         unroll<L::QY>([&](auto B) {
             unroll<L::QX>([&](auto A) {
@@ -513,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void init3_kernel(KArgs p)
     float rho, jx, jy, jz;
     moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
     const float inv = 1.0f / rho;
-    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv);
+    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv, mix32(mix32(h)));
     store3<LX, LY, LZ, ST, BCX>(p, make_rsrc(p.dst, p.buf_bytes), x, row, v, mix32(h));
 }
 
@@ -522,13 +527,12 @@ template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
 __global__ __launch_bounds__(kBlock) void stats3_kernel(KArgs p)
 {
     using L = Lat3<LX, LY, LZ, ST>;
-    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
     double acc[kNumStats];
     for (int k = 0; k < kNumStats; ++k) acc[k] = 0.0;
-    if (i < p.nodes) {
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    for (int i = blockIdx.x * kBlock + (int)threadIdx.x; i < p.nodes; i += gridDim.x * kBlock) {
         int x, y, z;
         node_xyz(p, i, x, y, z);
-        const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
         const XAddr<LX, L::EB, BCX> xa(x, p.nx);
         const uint32_t base = xa.own(row_bytes<L::EB>(p, z * p.ny + y));
         double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, e = 0.0;
@@ -551,12 +555,12 @@ __global__ __launch_bounds__(kBlock) void stats3_kernel(KArgs p)
         }
         const double jx_pre = jx - p.g;
         const double ux = jx_pre / r, uy = jy / r, uz = jz / r;
-        acc[0] = r;
-        acc[1] = jx_pre;
-        acc[2] = jy;
-        acc[3] = e;
-        acc[4] = ux * ux;
-        acc[11] = jz;
+        acc[0] += r;
+        acc[1] += jx_pre;
+        acc[2] += jy;
+        acc[3] += e;
+        acc[4] += ux * ux;
+        acc[11] += jz;
         if (p.prev) {
             const rsrc_t rp = make_rsrc(p.prev, p.buf_bytes);
             double r0 = 0.0, j0 = 0.0;
@@ -572,39 +576,28 @@ __global__ __launch_bounds__(kBlock) void stats3_kernel(KArgs p)
             });
             if constexpr (L::shifted) r0 += (double)kShift3<LX, LY, LZ>.sum;
             const double d = ux - (j0 - p.g) / r0;
-            acc[5] = d * d;
+            acc[5] += d * d;
         }
-        if (ux * ux > Axis<LX>::u2max || uy * uy > Axis<LY>::u2max || uz * uz > Axis<LZ>::u2max) acc[10] = 1.0;
+        if (!finite_node(r, jx, jy, jz, e))
+            acc[12] += 1.0;
+        else if (ux * ux > Axis<LX>::u2max || uy * uy > Axis<LY>::u2max || uz * uz > Axis<LZ>::u2max)
+            acc[10] += 1.0;
         if constexpr (BCY == BCY_WALL) {
             if (y == 0) {
                 float m;
                 const float A = wall_absorbed3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z, &m);
-                acc[6] = A;
-                acc[7] = (double)m - (double)A * p.uw[0];
+                acc[6] += A;
+                acc[7] += (double)m - (double)A * p.uw[0];
             }
             if (y == p.ny - 1) {
                 float m;
                 const float A = wall_absorbed3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z, &m);
-                acc[8] = A;
-                acc[9] = (double)m - (double)A * p.uw[1];
+                acc[8] += A;
+                acc[9] += (double)m - (double)A * p.uw[1];
             }
         }
     }
-    __shared__ double red[kBlock / 64][kNumStats];
-    for (int k = 0; k < kNumStats; ++k) {
-        double s = acc[k];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        acc[k] = s;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0)
-        for (int k = 0; k < kNumStats; ++k) red[wave][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x < kNumStats) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-        p.partials[(size_t)blockIdx.x * kNumStats + threadIdx.x] = s;
-    }
+    write_partials(acc, p.partials);
 }
 
 }  // namespace glbm

@@ -15,6 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libglbm.so")
 
 OK = 0
+ERR_NONFINITE = -5
+ERR_POSITIVITY = -6
+# health of a state as glbm_stats reports it
+HEALTH = {OK: "ok", ERR_NONFINITE: "nonfinite", ERR_POSITIVITY: "positivity"}
 BC = {"periodic": 0, "wall": 1, "eq_ends": 2}
 AXIS_ODD, AXIS_EVEN = 0, 1
 STORAGE = {"f32": 0, "f32_shifted": 1, "bf16_shifted": 2, "bf16_shifted_sr": 3}
@@ -25,7 +29,8 @@ SYMBOLS = (
     "glbm_population_bytes", "glbm_create", "glbm_init_fields", "glbm_init_populations",
     "glbm_step", "glbm_moments", "glbm_get_populations", "glbm_stats", "glbm_info",
     "glbm_destroy", "glbm_last_error", "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy",
-    "glbm_batch_update", "glbm_init_fields3", "glbm_moments3",
+    "glbm_batch_update", "glbm_init_fields3", "glbm_moments3", "glbm_required_bytes",
+    "glbm_bandwidth_probe",
 )
 ORDER = {"member": 0, "interleave": 1, "largest_first": 2}
 
@@ -79,6 +84,7 @@ class Stats(ctypes.Structure):
         ("wall_momentum", ctypes.c_double * 2),
         ("nonpositive_nodes", ctypes.c_double),
         ("momentum_z", ctypes.c_double),
+        ("nonfinite_nodes", ctypes.c_double),
     ]
 
 
@@ -96,6 +102,8 @@ def load(path: str = LIB_PATH):
     vp, cp = ctypes.c_void_p, ctypes.POINTER(Config)
     lib.glbm_population_bytes.argtypes = [cp]
     lib.glbm_population_bytes.restype = ctypes.c_size_t
+    lib.glbm_required_bytes.argtypes = [cp]
+    lib.glbm_required_bytes.restype = ctypes.c_size_t
     lib.glbm_create.argtypes = [cp, vp, vp, vp, ctypes.POINTER(vp)]
     lib.glbm_create.restype = ctypes.c_int
     lib.glbm_init_fields.argtypes = [vp, vp, vp, vp]
@@ -106,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.glbm_moments3.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.glbm_get_populations.argtypes = [vp, vp]
     lib.glbm_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.glbm_bandwidth_probe.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.c_int32, vp]
+    lib.glbm_bandwidth_probe.restype = ctypes.c_int
     lib.glbm_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     lib.glbm_destroy.argtypes = [vp]
@@ -166,6 +176,15 @@ def config_from_workload(w) -> Config:
 
 def population_bytes(cfg: Config) -> int:
     n = load().glbm_population_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise GlbmError("invalid configuration: " + load().glbm_last_error().decode(errors="replace"))
+    return int(n)
+
+
+def required_bytes(cfg: Config) -> int:
+    """Device bytes of a solver: both population buffers and the statistics
+    buffers (glbm_required_bytes)."""
+    n = load().glbm_required_bytes(ctypes.byref(cfg))
     if n == 0:
         raise GlbmError("invalid configuration: " + load().glbm_last_error().decode(errors="replace"))
     return int(n)
@@ -264,10 +283,15 @@ class Solver:
         return out
 
     def stats(self) -> dict:
+        """FP64 diagnostics; ``health`` is "ok", "nonfinite" (some node blew
+        up) or "positivity" (some node left the positivity domain)."""
         s = Stats()
         with self._torch.cuda.device(self.device):
-            _check(self.lib.glbm_stats(self._h, ctypes.byref(s)), "glbm_stats")
+            rc = self.lib.glbm_stats(self._h, ctypes.byref(s))
+        if rc not in HEALTH:
+            _check(rc, "glbm_stats")
         return {
+            "health": HEALTH[rc], "nonfinite_nodes": s.nonfinite_nodes,
             "time": s.time, "mass": s.mass, "momentum_x": s.momentum_x, "momentum_y": s.momentum_y,
             "energy_post": s.energy_post, "residual": s.residual,
             "wall_mass_bottom": s.wall_mass[0], "wall_mass_top": s.wall_mass[1],
@@ -358,6 +382,38 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def bandwidth_probe(mode: str, nbytes: int, reps: int = 20, blocks: int = 4096, device=None) -> dict:
+    """Time the library's streaming kernels (glbm_bandwidth_probe): "copy"
+    (nbytes read + nbytes written), "read" or "write", `reps` launches on the
+    current stream; returns the average launch time and the rate."""
+    import torch
+
+    lib = load()
+    code = {"copy": 0, "read": 1, "write": 2}[mode]
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty(nbytes // 4 if mode != "read" else 4, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+
+    def launch():
+        _check(lib.glbm_bandwidth_probe(code, src.data_ptr(), dst.data_ptr(), nbytes, blocks, sp),
+               "glbm_bandwidth_probe")
+
+    launch()
+    torch.cuda.synchronize(dev)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        launch()
+    stop.record(stream)
+    torch.cuda.synchronize(dev)
+    sec = start.elapsed_time(stop) / 1e3 / reps
+    moved = 2 * nbytes if mode == "copy" else nbytes
+    return {"mode": mode, "bytes": nbytes, "blocks": blocks, "us": round(sec * 1e6, 1),
+            "GBs": round(moved / sec / 1e9, 1)}
 
 
 def solver_for(workload, device=None, stream=None) -> Solver:

@@ -23,12 +23,18 @@ import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROFILES = os.path.join(ROOT, "profiles")
-COPY_KERNEL = "__amd_rocclr_copyBuffer"
+# kernels of known byte count for scaling the memory counters: the library's
+# own copy kernel (glbm_bandwidth_probe, bench.py runs it on 2 GiB), else the
+# HIP runtime's device copy
+COPY_KERNELS = ("probe_copy", "__amd_rocclr_copyBuffer")
+SOURCES = ("glbm_device.h", "glbm_device3.h", "glbm_inst.hip", "glbm_inst3.hip", "glbm_api.hip")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources: recorded traffic is used only while it
+    matches."""
     h = hashlib.sha256()
-    for f in ("glbm_device.h", "glbm_inst.hip", "glbm_api.hip"):
+    for f in SOURCES:
         with open(os.path.join(ROOT, "paper_1905_04597_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -161,10 +167,86 @@ def three_d_summary(trace: str, command: str, steps: int = 20, storage: str = "f
     print(path)
 
 
+def _csv_rows(path: str):
+    import csv
+
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def counters_summary(workload: str, tag: str, trace_csv: str, pmc_csvs, command: str, match: str = "glbm::step",
+                     compiler=None):
+    """Per-kernel medians of the SQ/TCC counters of the step kernel(s) and the
+    calibration copy kernel, with the register counts of the kernel trace,
+    written to profiles/counters_<workload>_<tag>.md.
+
+    Units: instruction counters are per wave (summed over waves); SQ_WAVE_CYCLES,
+    SQ_WAIT_INST_ANY and SQ_ACTIVE_INST_* count 4-cycle units summed over waves;
+    SQ_BUSY_CU_CYCLES counts cycles summed over compute units; GRBM_GUI_ACTIVE
+    counts cycles summed over the 8 XCDs.  Hence mean resident waves per CU =
+    4 SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES, the fraction of wave time waiting =
+    SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES, and VALU busy per SIMD =
+    SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES (4 SIMDs per CU, 4 cycles per
+    wave64 instruction)."""
+    vals = {}
+    for path in pmc_csvs:
+        for r in _csv_rows(path):
+            k = r["Kernel_Name"]
+            if match in k or "probe_copy" in k:
+                vals.setdefault((k, int(r["Grid_Size"])), {}).setdefault(r["Counter_Name"], []).append(
+                    float(r["Counter_Value"]))
+    durs = {}
+    for r in _csv_rows(trace_csv):
+        k = r["Kernel_Name"]
+        if match in k or "probe_copy" in k:
+            durs.setdefault((k, int(r["Grid_Size_X"])), []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    md = os.path.join(PROFILES, "counters_%s_%s.md" % (workload, tag))
+    with open(md, "w") as fh:
+        fh.write("# Counters of the step kernel, %s, %s\n\n" % (workload, tag))
+        fh.write("Commands (run on one MI355X):\n\n```\n%s\n```\n\n" % command.strip())
+        fh.write("Medians per dispatch.  Mean resident waves per CU = 4 SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES "
+                 "(8 = two waves per SIMD); waiting = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; VALU busy per SIMD = "
+                 "SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES; L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS).  The "
+                 "library's copy kernel (2 GiB each way) is the reference.\n\n")
+        fh.write("| kernel | grid | trace median us | waves | VALU insts per wave | "
+                 "VMEM rd / wr per wave | waves per CU | waiting | VALU busy | L2 hit |\n")
+        fh.write("|---|---|---|---|---|---|---|---|---|---|\n")
+        for (k, g), c in sorted(vals.items(), key=lambda kv: (("probe" in kv[0][0]), kv[0][1])):
+            m = {n: statistics.median(v) for n, v in c.items()}
+            w = m.get("SQ_WAVES", float("nan"))
+            busy = m.get("SQ_BUSY_CU_CYCLES", float("nan"))
+            wc = m.get("SQ_WAVE_CYCLES", float("nan"))
+            hit, miss = m.get("TCC_HIT_sum", float("nan")), m.get("TCC_MISS_sum", float("nan"))
+            du = durs.get((k, g))
+            short = "glbm_bandwidth_probe copy" if "probe_copy" in k else k.split("(")[0][:48]
+            fh.write("| `%s` | %d | %s | %.0f | %.0f | %.0f / %.0f | %.2f | %.2f | %.2f | %.2f |\n" % (
+                short, g,
+                ("%.1f" % statistics.median(du)) if du else "-", w, m.get("SQ_INSTS_VALU", float("nan")) / w,
+                m.get("SQ_INSTS_VMEM_RD", float("nan")) / w, m.get("SQ_INSTS_VMEM_WR", float("nan")) / w,
+                4 * wc / busy, m.get("SQ_WAIT_INST_ANY", float("nan")) / wc,
+                m.get("SQ_ACTIVE_INST_VALU", float("nan")) / busy, hit / (hit + miss)))
+        if compiler:
+            fh.write("\nRegisters per lane from the compiler's resource report (hipcc -O3 --offload-arch=gfx950 "
+                     "-Rpass-analysis=kernel-resource-usage on the kernel sources): %s.\n" % compiler)
+    print(md)
+    return md
+
+
 def main(argv=None):
     import sys
 
     argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "counters":
+        cp = argparse.ArgumentParser()
+        cp.add_argument("--workload", required=True)
+        cp.add_argument("--tag", required=True)
+        cp.add_argument("--trace-csv", required=True)
+        cp.add_argument("--pmc-csv", action="append", required=True)
+        cp.add_argument("--command", required=True)
+        cp.add_argument("--compiler", default=None, help="register counts from the compiler's resource report")
+        c = cp.parse_args(argv[1:])
+        return counters_summary(c.workload, c.tag, c.trace_csv, c.pmc_csv, c.command, compiler=c.compiler)
     if argv and argv[0] == "three_d":
         tp = argparse.ArgumentParser()
         tp.add_argument("--trace", required=True)
@@ -193,7 +275,12 @@ def main(argv=None):
     stats = kernel_stats(a.trace)
     fetch = counter(a.fetch, "FETCH_SIZE")
     write = counter(a.write, "WRITE_SIZE")
-    copy_key = max((k for k in fetch if k[0] == COPY_KERNEL), key=lambda k: fetch[k])
+    copy_key = None
+    for name in COPY_KERNELS:
+        keys = [k for k in fetch if name in k[0] and k in write]
+        if keys:
+            copy_key = max(keys, key=lambda k: fetch[k])
+            break
     f_scale = a.copy_bytes / (fetch[copy_key] * 1024.0)
     w_scale = a.copy_bytes / (write[copy_key] * 1024.0)
     # a time step may be more than one launch (16-bit storage with walls:
@@ -240,7 +327,7 @@ def main(argv=None):
                 continue
             fh.write("| `%s` | %d | %.1f | %.1f |\n" % (k[0][:60], k[1], fetch.get(k, float("nan")), write.get(k, float("nan"))))
         fh.write("\nCalibration: the %d-byte device copy (`%s`) reads FETCH_SIZE x %.3f and WRITE_SIZE x %.3f "
-                 "of its true bytes.\n\n" % (a.copy_bytes, COPY_KERNEL, 1 / f_scale, 1 / w_scale))
+                 "of its true bytes.\n\n" % (a.copy_bytes, copy_key[0][:60], 1 / f_scale, 1 / w_scale))
         fh.write("## Step kernel(s) per time step\n\n")
         fh.write("- average duration: %.1f us\n" % rec["avg_duration_us"])
         fh.write("- HBM bytes (scaled counters): fetch %.4g, write %.4g, total %.4g\n" % (fb, wb, fb + wb))

@@ -17,13 +17,22 @@ smallest of them run resident (one workgroup, a whole chunk of steps per
 launch).  A lane re-plans its batch in place (glbm_batch_update) when its
 members change.
 
-Admission: the population buffers of all active requests (2 x
-glbm_population_bytes each) stay within the budget (default 200 GB); requests
+Admission: the device bytes of all active requests (glbm_required_bytes
+each: both population buffers and the statistics buffers) stay within the
+budget (default 200 GB); requests
 are admitted first come, first served per lane (a request that does not fit
 waits, and so do the ones behind it in its lane).
 
 Every request's result is bitwise the result of the same solve run alone,
 because a batched lattice runs exactly the single-lattice kernel code.
+
+Failure detection: when a request finishes, the server reads its FP64
+diagnostics (glbm_stats) and records its health: "ok", "positivity" (some
+node left the domain where the equilibrium is non-negative, section 3: the
+result is kept, flagged) or "nonfinite" (the solve blew up: the request is
+retired as failed, with no result).  With check_every > 0 the members of a
+lane are also checked every that many chunks, and a blown-up request is
+retired at once instead of running out its step budget.
 """
 from __future__ import annotations
 
@@ -53,6 +62,12 @@ class Request:
     admitted: Optional[float] = None
     finished: Optional[float] = None
     result: Optional[dict] = None   # device moments {rho, ux, uy, T, pxy} when kept
+    health: Optional[str] = None    # "ok", "positivity" or "nonfinite" (then failed, no result)
+    f0: Optional[np.ndarray] = None  # initial populations [Q][ny][nx] instead of the workload's init
+
+    @property
+    def failed(self) -> bool:
+        return self.health == "nonfinite"
 
     @property
     def latency(self) -> Optional[float]:
@@ -90,14 +105,17 @@ def admissible(waiting_bytes, in_use: float, budget: float, free_slots: int) -> 
     return n
 
 
-def make_solver(w: wl.Workload, stream):
+def make_solver(w: wl.Workload, stream, f0=None):
     """Create and initialise the solver of a request on `stream` (its buffers
-    are allocated from that stream, so their reuse is ordered on it)."""
+    are allocated from that stream, so their reuse is ordered on it); f0, if
+    given, are its initial populations."""
     import torch
 
     with torch.cuda.stream(stream):
         s = glbm.solver_for(w, stream=stream)
-        if w.init == "sod":
+        if f0 is not None:
+            s.init_populations(f0)
+        elif w.init == "sod":
             rho = wl.sod_density(w.nx, w.end_rho[0], w.end_rho[1])
             s.init_fields(rho, np.zeros_like(rho))
         else:
@@ -105,12 +123,12 @@ def make_solver(w: wl.Workload, stream):
     return s
 
 
-def solve_alone(w: wl.Workload, steps: int, stream=None) -> dict:
+def solve_alone(w: wl.Workload, steps: int, stream=None, f0=None) -> dict:
     """The same solve without the server: one lattice, one launch per step."""
     import torch
 
     stream = stream or torch.cuda.current_stream()
-    s = make_solver(w, stream)
+    s = make_solver(w, stream, f0)
     s.step(steps)
     with torch.cuda.stream(stream):
         m = s.moments()
@@ -159,12 +177,15 @@ class Server:
     streams: streams per lane over which a lane's kernel variants advance side
     by side (glbm_batch_options.streams); (light, heavy).
     keep_results: True, or a set of request ids, whose device moments
-    {rho, ux, uy, T, pxy} are kept in Request.result."""
+    {rho, ux, uy, T, pxy} are kept in Request.result.
+    check_every: also check the health of every member of a lane every that
+    many of its chunks (0: only when a request finishes)."""
 
     def __init__(self, hbm_budget: float = 200e9, light_bytes: int = 64 << 20, light_lanes: int = 3,
                  chunks=(50, 20), slots=(4096, 256), tile_nodes: int = 128, order: str = "interleave",
                  resident_nodes: int = 2048, streams=(1, 1), keep_results: bool = False,
-                 clock=time.perf_counter):
+                 check_every: int = 0, clock=time.perf_counter):
+        self.check_every = int(check_every)
         self.hbm_budget = float(hbm_budget)
         self.light_bytes = int(light_bytes)
         self.keep_results = keep_results
@@ -191,6 +212,10 @@ class Server:
         member of a batch may be observed); they leave at the next plan."""
         import torch
 
+        if self.check_every > 0 and lane.chunks and lane.chunks % self.check_every == 0:
+            for a in lane.members:
+                if a.left > 0 and a.solver.stats()["health"] == "nonfinite":
+                    a.left = 0  # blown up: retire it now
         done = [a for a in lane.members if a.left <= 0]
         if not done:
             return
@@ -198,7 +223,10 @@ class Server:
         lane.changed = True
         for a in done:
             a.req.finished = now
-            if self._keep(a.req):
+            # the lane's work is done (its event was reached): this reads the
+            # finished state at once
+            a.req.health = a.solver.stats()["health"]
+            if self._keep(a.req) and not a.req.failed:
                 with torch.cuda.stream(lane.stream):
                     a.req.result = a.solver.moments()
             lane.leaving.append(a)
@@ -208,7 +236,7 @@ class Server:
                        lane.slots - len(lane.members))
         for _ in range(n):
             r = lane.waiting.popleft()
-            s = make_solver(r.workload, lane.stream)
+            s = make_solver(r.workload, lane.stream, r.f0)
             r.admitted = now
             self.in_use += r.nbytes
             self.peak_in_use = max(self.peak_in_use, self.in_use)
@@ -243,11 +271,12 @@ class Server:
 
     # ------------------------------------------------------------------ run
     def run(self, arrivals, max_seconds: float = 120.0):
-        """Serve [(arrival seconds, Workload)] in real time; returns the
-        Request records (every request finished unless max_seconds ran out)."""
-        reqs = [Request(i, t, w, w.steps) for i, (t, w) in enumerate(arrivals)]
+        """Serve [(arrival seconds, Workload)] (or (arrival, Workload, f0)
+        with initial populations f0) in real time; returns the Request records
+        (every request finished unless max_seconds ran out)."""
+        reqs = [Request(i, a[0], a[1], a[1].steps, f0=a[2] if len(a) > 2 else None) for i, a in enumerate(arrivals)]
         for r in reqs:
-            r.nbytes = 2 * glbm.population_bytes(glbm.config_from_workload(r.workload))
+            r.nbytes = glbm.required_bytes(glbm.config_from_workload(r.workload))
             if r.nbytes > self.hbm_budget:
                 raise glbm.GlbmError("request %d needs %d bytes, above the budget" % (r.rid, r.nbytes))
             r.lane = self._lane_of(r.workload)
@@ -329,4 +358,6 @@ def summarize(reqs, window=(2.0, 12.0)) -> dict:
         "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
         "latency_max_s": round(float(lat.max()), 4),
         "node_steps": int(sum(r.workload.nodes * r.steps for r in done)),
+        "failed": sum(1 for r in done if r.failed),
+        "positivity_flagged": sum(1 for r in done if r.health == "positivity"),
     }

@@ -2,6 +2,8 @@
 same seeded inputs and compare them."""
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 import oracle
@@ -14,10 +16,27 @@ ORACLE_BC = {"periodic": oracle.BC_PERIODIC, "wall": oracle.BC_WALL, "eq_ends": 
 TOL = {"f32": 1e-5, "f32_shifted": 1e-5, "bf16_shifted": 1e-3, "bf16_shifted_sr": 1e-3}
 # What each storage is held to per node in the parity cases.  FP32 deviation
 # storage is the FP32 path and meets 1e-5.  Plain FP32 keeps f ~ W and
-# re-rounds it every step: measured up to ~3e-5 on these cases.  BF16 keeps 8
-# significand bits: quantising a smooth 5% flow already costs ~4e-3 per node
-# and stochastic rounding adds noise each step (measured up to ~3e-2).
-BOUND = {"f32_shifted": 1e-5, "f32": 5e-5, "bf16_shifted_sr": 5e-2}
+# re-rounds it every step (the unoptimised comparison storage): measured up to
+# ~3e-5 on these cases, characterised at 5e-5.  BF16 deviation storage is held
+# to the stated 1e-3; the cases where its 8 significand bits cannot reach that
+# (measured on the GPU, and the floor of every rounding scheme emulated on the
+# CPU by tests/storage_emulation.py) are skipped by name with the measured
+# error as the reason.
+BOUND = {"f32_shifted": 1e-5, "f32": 5e-5, "bf16_shifted_sr": 1e-3, "bf16_shifted": 1e-3}
+
+
+def residual_bound(tol: float, res_ref: float, ux_ref) -> float:
+    """Bound on |r_gpu - r_ref| for the residual r = ||u_x(t) - u_x(t-1)||_2 /
+    ||u_x(t)||_2 when each snapshot of u_x is within tol (normwise L-inf, scale
+    max(max|u_x|, U_FLOOR)) of the oracle's: the difference field is off by at
+    most 2 tol scale per node, i.e. 2 tol scale sqrt(n) in the 2-norm, and the
+    normalisation adds tol relative."""
+    u = np.asarray(ux_ref, dtype=np.float64).ravel()
+    scale = max(float(np.max(np.abs(u))), U_FLOOR)
+    norm = float(np.sqrt(np.sum(u * u)))
+    return tol * res_ref + 2.0 * tol * scale * math.sqrt(u.size) / norm
+
+
 # Floors of the error scale for fields whose reference vanishes (u = 0 at
 # rest, u_y in a channel, Pxy of an equilibrium): velocities are measured
 # against at least 1e-2 (lattice units, ~1e-2 c_s) and the shear moment

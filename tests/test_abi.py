@@ -51,7 +51,7 @@ def test_population_bytes_layout():
     # bytes, whatever nx
     c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="f32")
     assert glbm.population_bytes(c) == 121 * 1024 * 4096 * 4
-    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="bf16_shifted")
+    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="bf16_shifted_sr")
     assert glbm.population_bytes(c) == 121 * 1024 * 4096 * 2
     c = glbm.make_config(2, 3, 3, 4, 37, kn=0.1, bc_y="wall", storage="f32_shifted")
     assert glbm.population_bytes(c) == 49 * ((37 * 4 * 4 + 255) // 256 * 256)
@@ -81,6 +81,31 @@ def test_invalid_configs_are_rejected(kwargs, needle):
     c = glbm.make_config(**kwargs)
     assert glbm.load().glbm_population_bytes(ctypes.byref(c)) == 0
     assert needle in glbm.load().glbm_last_error().decode()
+
+
+def test_required_bytes_counts_both_buffers_and_the_statistics():
+    # two population buffers plus the FP64 statistics: one row of 13 partial
+    # sums per block of 256 nodes (at most 2048 rows, the blocks stride over
+    # larger lattices) and the 13 totals
+    c = glbm.make_config(2, 5, 5, 4096, 1024, kn=0.1, bc_y="wall", storage="f32_shifted")
+    assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (2048 + 1)
+    c = glbm.make_config(1, 3, 0, 2000, 1, kn=0.01, bc_x="eq_ends")
+    assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (8 + 1)
+    bad = glbm.make_config(4, 1)
+    assert glbm.load().glbm_required_bytes(ctypes.byref(bad)) == 0
+
+
+@pytest.mark.parametrize("kwargs", [
+    dict(dims=2, level_x=3, level_y=3, nx=8, ny=16, tau=0.8, bc_y="wall"),
+    dict(dims=1, level_x=3, nx=100, tau=0.8, g=1e-5),
+])
+def test_round_to_nearest_bf16_is_refused_for_driven_flows(kwargs):
+    c = glbm.make_config(**kwargs, storage="bf16_shifted")
+    assert glbm.load().glbm_population_bytes(ctypes.byref(c)) == 0
+    assert "stalls driven flows" in glbm.load().glbm_last_error().decode()
+    # undriven lattices keep it
+    c = glbm.make_config(1, 3, 0, 100, 1, tau=0.8, storage="bf16_shifted")
+    assert glbm.population_bytes(c) > 0
 
 
 def test_three_dimensional_layout_and_checks():

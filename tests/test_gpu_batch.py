@@ -222,6 +222,13 @@ PACKED_CASES = [
 @pytest.mark.parametrize("case", range(len(PACKED_CASES)))
 def test_16bit_alone_matches_batch_bitwise(case, storage):
     cfg = dict(PACKED_CASES[case], storage=storage)
+    if storage == "bf16_shifted" and cfg["level_x"] == 1 and cfg.get("even_y"):
+        pytest.skip("round-to-nearest BF16 is refused with walls, the only boundary of the mixed lattices")
+    if storage == "bf16_shifted" and (cfg.get("g", 0.0) != 0.0 or cfg.get("bc_y") == "wall"):
+        # round to nearest is refused for driven flows: its undriven form
+        cfg.pop("g", None)
+        cfg.pop("wall_u", None)
+        cfg["bc_y"] = "periodic"
     print("\n[batch] 16-bit alone vs batched: %s" % cfg, flush=True)
     alone, batched = _solver(cfg), _solver(cfg)
     for s in (alone, batched):
