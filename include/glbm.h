@@ -211,6 +211,18 @@ int glbm_get_populations(glbm_t *h, float *out);
  * GLBM_OK. */
 int glbm_stats(glbm_t *h, glbm_stats_t *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): as
+ * glbm_stats, but the FP64 partial sums go through a fixed device array of
+ * the library (2049 x 13 doubles, 213 KB, held once per GPU until the process
+ * ends) instead of buffers allocated on the first call; it allocates nothing.
+ * Any lattice the library accepts fits (the statistics blocks stride over the
+ * nodes; a larger need would return GLBM_ERR_INVALID).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (other host threads, other
+ * streams) race and must be serialised by the caller.  Same statuses as
+ * glbm_stats. */
+int glbm_stats_static(glbm_t *h, glbm_stats_t *out);
+
 /* Derived parameters: relaxation time, collision frequency 1/(tau + 1/2),
  * number of velocities, current time.  Host pointers; any may be NULL. */
 int glbm_info(const glbm_t *h, double *tau, double *omega, int32_t *nvel, int64_t *time);

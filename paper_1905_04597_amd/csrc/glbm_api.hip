@@ -536,6 +536,58 @@ int glbm_destroy(glbm_t *h)
 
 }  // extern "C"
 
+// ------------------------------------------ statistics without allocation
+// glbm_stats_static: glbm_stats for callers that cannot allocate device
+// memory.  The partial sums and totals go through `scratch`, a file-scope
+// device array that every GPU the library runs on holds once (it stays
+// allocated until the process ends).  Host code never passes the array's name
+// to a kernel or copy: it uses the device address hipGetSymbolAddress gives
+// for the current device, fetched once per device and kept.
+constexpr int kScratchRows = kStatBlocks + 1;  // partial-sum rows, then the totals
+static __device__ __align__(256) double scratch[kScratchRows * kNumStats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (made current for the lookup).
+int scratch_on(int dev, double **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(GLBM_ERR_INVALID, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void *ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "locating the statistics scratch");
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GLBM_OK;
+}
+}  // namespace
+
+extern "C" int glbm_stats_static(glbm_t *h, glbm_stats_t *out)
+{
+    if (!h || !out) return fail(GLBM_ERR_INVALID, "NULL argument");
+    if (!h->ready) return fail(GLBM_ERR_STATE, "stats before init");
+    const int blocks = stat_blocks((int64_t)h->base.nodes);
+    if (blocks + 1 > kScratchRows)
+        return fail(GLBM_ERR_INVALID, "statistics need %d partial rows, the scratch holds %d", blocks, kScratchRows - 1);
+    double *ptr = nullptr;
+    const int rc = scratch_on(h->device, &ptr);
+    if (rc != GLBM_OK) return rc;
+    double hout[kNumStats];
+    // every block writes its whole row and the reduction writes every total,
+    // so nothing in the scratch needs clearing between calls
+    return stats_through(h, ptr, ptr + (size_t)kStatBlocks * kNumStats, hout, out);
+}
+// ------------------------------------------ end of statistics without allocation
+
 // ------------------------------------------------------------------ batches
 //
 // All device tables of a batch live in one allocation, uploaded from a

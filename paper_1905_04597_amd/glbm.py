@@ -30,7 +30,7 @@ SYMBOLS = (
     "glbm_step", "glbm_moments", "glbm_get_populations", "glbm_stats", "glbm_info",
     "glbm_destroy", "glbm_last_error", "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy",
     "glbm_batch_update", "glbm_init_fields3", "glbm_moments3", "glbm_required_bytes",
-    "glbm_bandwidth_probe",
+    "glbm_stats_static", "glbm_bandwidth_probe",
 )
 ORDER = {"member": 0, "interleave": 1, "largest_first": 2}
 
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH):
     lib.glbm_moments3.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.glbm_get_populations.argtypes = [vp, vp]
     lib.glbm_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.glbm_stats_static.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.glbm_bandwidth_probe.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.c_int32, vp]
     lib.glbm_bandwidth_probe.restype = ctypes.c_int
     lib.glbm_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -129,7 +130,7 @@ def load(path: str = LIB_PATH):
     for name in ("glbm_init_fields", "glbm_init_populations", "glbm_step", "glbm_moments",
                  "glbm_get_populations", "glbm_stats", "glbm_info", "glbm_destroy",
                  "glbm_batch_create", "glbm_batch_step", "glbm_batch_destroy", "glbm_batch_update",
-                 "glbm_init_fields3", "glbm_moments3"):
+                 "glbm_init_fields3", "glbm_moments3", "glbm_stats_static"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
