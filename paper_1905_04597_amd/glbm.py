@@ -283,12 +283,15 @@ class Solver:
             _check(self.lib.glbm_get_populations(self._h, self._ptr(out)), "glbm_get_populations")
         return out
 
-    def stats(self) -> dict:
+    def stats(self, static: bool = False) -> dict:
         """FP64 diagnostics; ``health`` is "ok", "nonfinite" (some node blew
-        up) or "positivity" (some node left the positivity domain)."""
+        up) or "positivity" (some node left the positivity domain).  static:
+        through glbm_stats_static (no device allocation; calls on one GPU must
+        not overlap)."""
         s = Stats()
+        fn = self.lib.glbm_stats_static if static else self.lib.glbm_stats
         with self._torch.cuda.device(self.device):
-            rc = self.lib.glbm_stats(self._h, ctypes.byref(s))
+            rc = fn(self._h, ctypes.byref(s))
         if rc not in HEALTH:
             _check(rc, "glbm_stats")
         return {

@@ -27,7 +27,9 @@ Every request's result is bitwise the result of the same solve run alone,
 because a batched lattice runs exactly the single-lattice kernel code.
 
 Failure detection: when a request finishes, the server reads its FP64
-diagnostics (glbm_stats) and records its health: "ok", "positivity" (some
+diagnostics (glbm_stats_static, which allocates nothing: the server's calls
+come from one thread and each one synchronises, so they never overlap) and
+records its health: "ok", "positivity" (some
 node left the domain where the equilibrium is non-negative, section 3: the
 result is kept, flagged) or "nonfinite" (the solve blew up: the request is
 retired as failed, with no result).  With check_every > 0 the members of a
@@ -214,7 +216,7 @@ class Server:
 
         if self.check_every > 0 and lane.chunks and lane.chunks % self.check_every == 0:
             for a in lane.members:
-                if a.left > 0 and a.solver.stats()["health"] == "nonfinite":
+                if a.left > 0 and a.solver.stats(static=True)["health"] == "nonfinite":
                     a.left = 0  # blown up: retire it now
         done = [a for a in lane.members if a.left <= 0]
         if not done:
@@ -225,7 +227,7 @@ class Server:
             a.req.finished = now
             # the lane's work is done (its event was reached): this reads the
             # finished state at once
-            a.req.health = a.solver.stats()["health"]
+            a.req.health = a.solver.stats(static=True)["health"]
             if self._keep(a.req) and not a.req.failed:
                 with torch.cuda.stream(lane.stream):
                     a.req.result = a.solver.moments()
