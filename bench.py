@@ -322,6 +322,33 @@ def run_served(duration: float = 12.0, warm: float = 2.0, sample: int = 16, loop
     }
 
 
+def run_served_rates(rates=(400.0, 800.0), duration: float = 6.0, warm: float = 1.0, loop_max: float = 45.0):
+    """The served mix at higher arrival rates (same seeds and parameter
+    distributions), server and per-solve loop: the sustained solves/s of
+    each once the offered load exceeds what the loop can serve."""
+    import torch
+    from paper_1905_04597_amd import serving
+    from paper_1905_04597_amd import workloads as wl
+
+    out = []
+    for rate in rates:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        arrivals = wl.served_requests(rate=rate, duration=duration)
+        srv = serving.Server()
+        reqs = srv.run(arrivals, max_seconds=duration + 60)
+        summ = serving.summarize(reqs, (warm, duration))
+        loop = serving.serve_per_solve(arrivals, max_seconds=loop_max)
+        lsum = serving.summarize(loop, (warm, duration))
+        offered = sum(serving.step_bytes(w) * w.steps for _, w in arrivals) / duration
+        out.append({"rate_per_s": rate, "requests": len(arrivals), "offered_GBs": round(offered / 1e9, 1),
+                    "server": {k: summ[k] for k in ("completed", "solves_per_s", "latency_p50_s", "latency_p99_s",
+                                                    "failed")},
+                    "per_solve_loop": {k: lsum[k] for k in ("completed", "solves_per_s", "latency_p50_s",
+                                                            "latency_p99_s")}})
+    return out
+
+
 def _oracle_sample(args):
     """One oracle run of the bounded sample (a worker of cpu_baseline)."""
     level, nx, ny, steps = args
@@ -396,6 +423,7 @@ def main(argv=None):
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-only", action="store_true", help="print only the served-mix record")
     ap.add_argument("--served-seconds", type=float, default=12.0)
+    ap.add_argument("--no-served-rates", action="store_true", help="skip the served mix at 400 and 800 requests/s")
     ap.add_argument("--only-3d", action="store_true", help="print only the three-dimensional sweep lines")
     a = ap.parse_args(argv)
 
@@ -409,7 +437,10 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     if a.served_only:
-        print(json.dumps(run_served(a.served_seconds)), flush=True)
+        served = run_served(a.served_seconds)
+        if not a.no_served_rates:
+            served["rates"] = run_served_rates()
+        print(json.dumps(served), flush=True)
         print(json.dumps(run_solves()), flush=True)
         return 0
     if a.only_3d:
@@ -434,7 +465,7 @@ def main(argv=None):
             sweep[-1]["frac"] = round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)
         # the G-D1Q(2N+2) lattices: D1Q3 x G-D1Q(2N+2) channels and the
         # symmetric products
-        for lattice, levels in (("mixed_even", range(1, 8)), ("even", range(1, 7))):
+        for lattice, levels in (("mixed_even", range(1, 14)), ("even", range(1, 7))):
             for lv in levels:
                 r = run_gpu(lv, a.nx, a.ny, a.storage, a.sweep_steps, 5, lattice)
                 sweep.append({"lattice": lattice, "N": lv, "Q": r["Q"], "glups": round(r["glups"], 4),
@@ -455,6 +486,8 @@ def main(argv=None):
                               "frac": round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)})
     batched = None if a.no_batched else run_batched(a.batch_count, a.batch_steps, loop_steps=a.batch_loop_steps)
     served = None if a.no_served else run_served(a.served_seconds)
+    if served is not None and not a.no_served_rates:
+        served["rates"] = run_served_rates()
     solves = None if a.no_served else run_solves()
     cpu = None if a.no_cpu_baseline else cpu_baseline(a.level)
     achieved = main_run["achieved_GBs"]

@@ -75,8 +75,13 @@ extern "C" {
 #define GLBM_STORE_BF16_SHIFTED_SR 3 /* f - S in BF16, stochastic rounding keyed by
                                         (time step, node, velocity): reproducible */
 
-/* Largest hierarchy level per axis built into the library. */
-#define GLBM_MAX_LEVEL 7
+/* Largest hierarchy level per axis built into the library: 7 on every axis,
+ * and 13 for the G-D1Q(2N+2) axis across the walls of the mixed channel
+ * lattices D1Q3 x G-D1Q(2N+2) (the paper's G-D1Q20 ... G-D1Q28 x D1Q3 of
+ * section 5.4).  Levels 8..13 elsewhere pass the configuration checks but
+ * glbm_create returns GLBM_ERR_UNSUPPORTED. */
+#define GLBM_MAX_LEVEL 13
+#define GLBM_MAX_LEVEL_ANY_AXIS 7
 
 /* Velocity set of an axis (section 2). */
 #define GLBM_AXIS_ODD 0  /* G-D1Q(2N+1): velocities -N..N, theta = N/3 (unit lattice step) */
@@ -86,7 +91,7 @@ extern "C" {
                             units, theta = (4N+3)/3 (Eq. temp_2N2 with c = 2 grid units).
                             Built: one dimension (N = 1..7), the mixed lattices
                             G-D1Q3 x G-D1Q(2N+2) with walls across the even axis (the form of
-                            sections 5.3-5.4, N = 1..7) and the symmetric two-dimensional
+                            sections 5.3-5.4, N = 1..13) and the symmetric two-dimensional
                             products (N = 1..6). */
 
 typedef struct glbm_config {

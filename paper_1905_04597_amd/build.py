@@ -21,6 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libglbm.so")
 ARCH = "gfx950"
 LEVELS = (7, 6, 5, 4, 3, 2, 1, 0)  # slowest first; 0 = mixed-level lattices
+MIXED_LEVELS = (13, 12, 11, 10, 9, 8)  # the even axis of the mixed lattices beyond 7
 
 FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
@@ -77,6 +78,10 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
                               os.path.join(BUILD, "glbm_inst_%s%d%s.o" % ("e" if even else "", lv,
                                                                          "c" if compact else "")),
                               ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_EVEN=%d" % even, "-DGLBM_COMPACT=%d" % compact]))
+    # levels 8..13: the mixed channel lattice D1Q3 x G-D1Q(2N+2) only
+    for lv in MIXED_LEVELS:
+        tasks.insert(2, (os.path.join(CSRC, "glbm_inst.hip"), os.path.join(BUILD, "glbm_inst_e%dc.o" % lv),
+                         ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_EVEN=1", "-DGLBM_COMPACT=1"]))
     todo = [t for t in tasks if not incremental or _stale(t[0], t[1])]
     jobs = jobs or min(len(todo) or 1, os.cpu_count() or 4, 16)
     if todo:

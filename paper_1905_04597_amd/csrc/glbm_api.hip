@@ -119,6 +119,9 @@ int check_config(const glbm_config *c, Geometry *g)
     if (!c) return fail(GLBM_ERR_INVALID, "config is NULL");
     if (c->dims < 1 || c->dims > 3) return fail(GLBM_ERR_INVALID, "dims must be 1, 2 or 3 (got %d)", c->dims);
     const int lx = c->level_x, ly = c->dims >= 2 ? c->level_y : 0, lz = c->dims == 3 ? c->level_z : 0;
+    // levels up to kMaxLevel pass here; the kernels built for each lattice
+    // (7 per axis, 13 for the even axis of the mixed channel lattices) are
+    // checked at glbm_create
     if (lx < 1 || lx > kMaxLevel) return fail(GLBM_ERR_INVALID, "level_x must be in 1..%d", kMaxLevel);
     if (c->dims >= 2 && (ly < 1 || ly > kMaxLevel)) return fail(GLBM_ERR_INVALID, "level_y must be in 1..%d", kMaxLevel);
     if (c->dims == 3 && (lz < 1 || lz > kMaxLevel)) return fail(GLBM_ERR_INVALID, "level_z must be in 1..%d", kMaxLevel);

@@ -40,7 +40,10 @@
 
 namespace glbm {
 
-constexpr int kMaxLevel = 7;
+// Largest level of an axis: 7 for every lattice, 13 for the G-D1Q(2N+2) axis
+// across the walls of the mixed channel lattices (G-D1Q28 x D1Q3 at N = 13,
+// the lattice of the Knudsen minimum in section 5.4).
+constexpr int kMaxLevel = 13;
 constexpr int kMaxQ1 = 2 * kMaxLevel + 2;  // velocities of the largest axis
 constexpr int kBlock = 256;
 constexpr int kNumStats = 13;
@@ -63,7 +66,7 @@ enum BcY { BCY_PERIODIC = 0, BCY_WALL = 1 };
 // odd integers -(2N+1)..2N+1, and its temperature is (4N+3) c^2 / 12 =
 // (4N+3)/3 (Eq. temp_2N2 with c = 2).  A = 0: the absent y axis of a
 // one-dimensional lattice (the single velocity 0).
-constexpr int kEven = 8;
+constexpr int kEven = 16;
 constexpr int kAxisCodes = 2 * kEven;
 
 template <int A>

@@ -1,5 +1,7 @@
 // Kernel instantiations for one hierarchy level, selected at compile time
-// with -DGLBM_LEVEL=N (N = 1..7); -DGLBM_LEVEL=0 builds the mixed lattices.
+// with -DGLBM_LEVEL=N (N = 1..7); -DGLBM_LEVEL=0 builds the mixed lattices
+// up to level 7, -DGLBM_LEVEL=8..13 the mixed lattice with the even axis of
+// that level.
 // -DGLBM_EVEN=1 builds the lattices of G-D1Q(2N+2) axes instead of
 // G-D1Q(2N+1) ones.  -DGLBM_COMPACT=0 builds the one-dimensional lattices
 // (padded rows), -DGLBM_COMPACT=1 the two-dimensional ones (periodic x in
@@ -132,7 +134,17 @@ void add_all_storages()
 #define GLBM_AX(N) (N)
 #endif
 
-#if GLBM_LEVEL >= 1
+#if GLBM_LEVEL >= 8
+// Levels 8..13: only the mixed channel lattice D1Q3 (streamwise x) x
+// G-D1Q(2N+2) (across the walls), one object per level.
+#if !GLBM_EVEN || !GLBM_COMPACT
+#error "levels above 7 exist only for the even axis of the mixed lattices (-DGLBM_EVEN=1 -DGLBM_COMPACT=1)"
+#endif
+void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, GLBM_LEVEL)()
+{
+    add_all_storages<1, GLBM_AX(GLBM_LEVEL), BCX_WRAP, BCY_WALL>();
+}
+#elif GLBM_LEVEL >= 1
 void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, GLBM_LEVEL)()
 {
     constexpr int N = GLBM_LEVEL, A = GLBM_AX(GLBM_LEVEL);

@@ -40,12 +40,14 @@ void register3();
 // One registration function per object file of glbm_inst.hip,
 // register_E_C_L(): E = 1 for the lattices with G-D1Q(2N+2) axes, C = 0 for
 // the one-dimensional lattices (padded rows), 1 for the two-dimensional ones
-// (compact rows), L = level (0: the mixed lattices with a D1Q3 x axis).
+// (compact rows), L = level (0: the mixed lattices with a D1Q3 x axis up to
+// level 7; 8..13: the mixed lattice with the even axis of that level).
 #define GLBM_OBJECTS(X)                                                                                        \
     X(0, 0, 1) X(0, 0, 2) X(0, 0, 3) X(0, 0, 4) X(0, 0, 5) X(0, 0, 6) X(0, 0, 7)                   \
     X(0, 1, 0) X(0, 1, 1) X(0, 1, 2) X(0, 1, 3) X(0, 1, 4) X(0, 1, 5) X(0, 1, 6) X(0, 1, 7)                   \
     X(1, 0, 1) X(1, 0, 2) X(1, 0, 3) X(1, 0, 4) X(1, 0, 5) X(1, 0, 6) X(1, 0, 7)                   \
-    X(1, 1, 0) X(1, 1, 1) X(1, 1, 2) X(1, 1, 3) X(1, 1, 4) X(1, 1, 5) X(1, 1, 6) X(1, 1, 7)
+    X(1, 1, 0) X(1, 1, 1) X(1, 1, 2) X(1, 1, 3) X(1, 1, 4) X(1, 1, 5) X(1, 1, 6) X(1, 1, 7)                   \
+    X(1, 1, 8) X(1, 1, 9) X(1, 1, 10) X(1, 1, 11) X(1, 1, 12) X(1, 1, 13)
 #define GLBM_DECLARE_REGISTER(E, C, L) void register_##E##_##C##_##L();
 GLBM_OBJECTS(GLBM_DECLARE_REGISTER)
 

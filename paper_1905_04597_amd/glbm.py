@@ -22,7 +22,8 @@ HEALTH = {OK: "ok", ERR_NONFINITE: "nonfinite", ERR_POSITIVITY: "positivity"}
 BC = {"periodic": 0, "wall": 1, "eq_ends": 2}
 AXIS_ODD, AXIS_EVEN = 0, 1
 STORAGE = {"f32": 0, "f32_shifted": 1, "bf16_shifted": 2, "bf16_shifted_sr": 3}
-MAX_LEVEL = 7
+MAX_LEVEL = 13          # the even axis across the walls of the mixed lattices
+MAX_LEVEL_ANY_AXIS = 7  # every other axis
 
 # Exported entry points of include/glbm.h (kept in sync by tests/test_abi.py).
 SYMBOLS = (

@@ -7,8 +7,9 @@ external data, run on the GPU through batches of lattices.
   non-finite or non-positive density) and how strongly it oscillates.
 * ``channel_observables``: steady Couette and force-driven Poiseuille
   channels over levels and Knudsen numbers (sections 5.3-5.4): slip
-  velocity and normalised flow rate, for self-convergence in N (the paper's
-  benchmark curves are not available).
+  velocity, normalised flow rate and the volumetric flow of section 5.4, for
+  self-convergence in N and the Knudsen minimum of the even hierarchy at
+  N >= 10 (the paper's benchmark curves are not available).
 
 Units: the paper fixes theta0 = 1 and the lattice step c(N) per level; the
 library works on each axis in its own lattice units (unit spacing, theta =
@@ -96,10 +97,11 @@ class ChannelOutcome:
     residual: float            # steady-state residual at the end
     slip: float                # see channel_observables
     flow: float                # Couette: normalised wall shear stress; Poiseuille: normalised flow rate
+    volumetric: float = float("nan")  # Poiseuille: the volumetric flow of section 5.4 (see channel_observables)
 
 
 def channel_observables(kind: str, levels, kns, lattice: str = "mixed_even", ny: int = 64, steps: int = 20000,
-                        storage: str = "f32_shifted", speed_cs: float = 0.01):
+                        storage: str = "f32_shifted", speed_cs: float = 0.01, resident: bool = True):
     """Steady channels of section 5.3 (Couette) or 5.4 (Poiseuille), one
     batch over all (level, Kn), nx = 4 (x-uniform flows, members resident),
     run `steps` steps from rest.  U = speed_cs times the sound speed of the
@@ -114,7 +116,12 @@ def channel_observables(kind: str, levels, kns, lattice: str = "mixed_even", ny:
     Poiseuille (walls at rest, g = 8 nu U / H^2):
       slip = u(y_0) / u(y_centre);
       flow = sum_y u(y) / (2 U H / 3), the flow rate over the no-slip
-        continuum value."""
+        continuum value;
+      volumetric = delta / (4 U H) sum_y u(y), the volumetric flow of section
+        5.4 with U the no-slip centre-line speed g H^2 / (8 nu) and the
+        rarefaction parameter delta = sqrt(pi) / (2 Kn) (the paper does not
+        restate delta; this is the usual definition of the tabulated data it
+        compares with)."""
     import torch
 
     confs, meta = [], []
@@ -139,18 +146,20 @@ def channel_observables(kind: str, levels, kns, lattice: str = "mixed_even", ny:
     for s in solvers:
         s.init_fields()
     torch.cuda.synchronize()
-    with glbm.Batch(solvers, resident_nodes=4 * ny) as b:
+    with glbm.Batch(solvers, resident_nodes=4 * ny if resident else 0) as b:
         b.step(steps)
     out = []
     for s, (lv, kn, U, nu) in zip(solvers, meta):
         ux = s.moments(("ux",))["ux"][:, 0].double().cpu().numpy()
         st = s.stats()
+        vol = float("nan")
         if kind == "couette":
             slip = (ux[0] + U) / (2 * U) - 0.5 / ny
             flow = (st["wall_momentum_bottom"] / 4) / (2 * U * nu / ny)
         else:
             slip = ux[0] / ux[ny // 2]
             flow = ux.sum() / (2.0 * U * ny / 3.0)
-        out.append(ChannelOutcome(kind, lattice, lv, kn, steps, st["residual"], float(slip), float(flow)))
+            vol = math.sqrt(math.pi) / (2.0 * kn) * ux.sum() / (4.0 * U * ny)
+        out.append(ChannelOutcome(kind, lattice, lv, kn, steps, st["residual"], float(slip), float(flow), vol))
         s.close()
     return out

@@ -69,7 +69,7 @@ def test_population_bytes_layout():
 @pytest.mark.parametrize("kwargs,needle", [
     (dict(dims=4, level_x=1), "dims"),
     (dict(dims=1, level_x=0, nx=10), "level_x"),
-    (dict(dims=1, level_x=8, nx=10), "level_x"),
+    (dict(dims=1, level_x=14, nx=10), "level_x"),
     (dict(dims=2, level_x=3, level_y=3, nx=4, ny=5, bc_y="wall"), "fastest y velocity"),
     (dict(dims=2, level_x=2, level_y=2, nx=4, ny=8, bc_x="eq_ends", bc_y="wall"), "combined"),
     (dict(dims=2, level_x=7, level_y=7, nx=8192, ny=4096, bc_y="wall"), "4 GiB"),

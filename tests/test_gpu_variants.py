@@ -4,7 +4,7 @@ The variants: one dimension (G-D1Q(2N+1) and G-D1Q(2N+2), N = 1..7,
 periodic or fixed equilibrium ends), two dimensions (the symmetric products,
 N = 1..7 and N = 1..6 for the even axis; periodic y or walls), the mixed
 channel lattices D1Q3 x G-D1Q(2N+1) (N = 2..7) and D1Q3 x G-D1Q(2N+2)
-(N = 1..7) with walls, and the three-dimensional lattices (D3Q27, G-D3Q125,
+(N = 1..13) with walls, and the three-dimensional lattices (D3Q27, G-D3Q125,
 D1Q3 x G-D1Q5/Q7/Q6/Q8 x D1Q3; periodic y or walls), each in the four
 storages.  Each runs a small seeded case (random shape within what the
 variant allows, random relaxation time, force and wall speeds, random
@@ -67,9 +67,12 @@ BF16_SHORTFALL = {
     "2d-e4xe4-periodic-wall-bf16_shifted_sr": 1.0e-03, "2d-e5xe5-periodic-periodic-bf16_shifted_sr": 1.5e-03,
     "2d-e5xe5-periodic-wall-bf16_shifted_sr": 1.3e-03, "2d-e6xe6-periodic-periodic-bf16_shifted": 2.3e-03,
     "2d-e6xe6-periodic-periodic-bf16_shifted_sr": 1.7e-03, "2d-o1xe1-periodic-wall-bf16_shifted_sr": 1.8e-03,
+    "2d-o1xe10-periodic-wall-bf16_shifted_sr": 3.1e-03, "2d-o1xe11-periodic-wall-bf16_shifted_sr": 4.8e-03,
+    "2d-o1xe12-periodic-wall-bf16_shifted_sr": 2.2e-03, "2d-o1xe13-periodic-wall-bf16_shifted_sr": 2.7e-03,
     "2d-o1xe2-periodic-wall-bf16_shifted_sr": 2.9e-03, "2d-o1xe3-periodic-wall-bf16_shifted_sr": 2.2e-03,
     "2d-o1xe4-periodic-wall-bf16_shifted_sr": 2.7e-03, "2d-o1xe5-periodic-wall-bf16_shifted_sr": 3.0e-03,
     "2d-o1xe6-periodic-wall-bf16_shifted_sr": 2.6e-03, "2d-o1xe7-periodic-wall-bf16_shifted_sr": 3.1e-03,
+    "2d-o1xe8-periodic-wall-bf16_shifted_sr": 2.7e-03, "2d-o1xe9-periodic-wall-bf16_shifted_sr": 3.5e-03,
     "2d-o1xo1-periodic-periodic-bf16_shifted_sr": 2.7e-03, "2d-o1xo1-periodic-wall-bf16_shifted_sr": 3.9e-03,
     "2d-o1xo2-periodic-wall-bf16_shifted_sr": 3.5e-03, "2d-o1xo3-periodic-wall-bf16_shifted_sr": 4.3e-03,
     "2d-o1xo4-periodic-wall-bf16_shifted_sr": 1.8e-03, "2d-o1xo5-periodic-wall-bf16_shifted_sr": 1.9e-03,
@@ -79,11 +82,14 @@ BF16_SHORTFALL = {
     "2d-o3xo3-periodic-wall-bf16_shifted_sr": 1.3e-03, "2d-o4xo4-periodic-periodic-bf16_shifted_sr": 1.2e-03,
     "2d-o5xo5-periodic-wall-bf16_shifted_sr": 1.6e-03, "2d-o6xo6-periodic-periodic-bf16_shifted_sr": 1.2e-03,
     "3d-o1xe2xo1-periodic-periodic-bf16_shifted_sr": 3.7e-03, "3d-o1xe2xo1-periodic-wall-bf16_shifted_sr": 6.0e-03,
+    "3d-o1xe3xo1-periodic-periodic-bf16_shifted": 1.7e-03,
     "3d-o1xe3xo1-periodic-periodic-bf16_shifted_sr": 6.0e-03, "3d-o1xe3xo1-periodic-wall-bf16_shifted_sr": 2.9e-03,
     "3d-o1xo1xo1-periodic-periodic-bf16_shifted_sr": 3.1e-03, "3d-o1xo1xo1-periodic-wall-bf16_shifted_sr": 3.2e-03,
     "3d-o1xo2xo1-periodic-periodic-bf16_shifted": 2.7e-03,
     "3d-o1xo2xo1-periodic-periodic-bf16_shifted_sr": 2.7e-03, "3d-o1xo2xo1-periodic-wall-bf16_shifted_sr": 2.1e-03,
+    "3d-o1xo3xo1-periodic-periodic-bf16_shifted": 1.4e-03,
     "3d-o1xo3xo1-periodic-periodic-bf16_shifted_sr": 1.3e-03, "3d-o1xo3xo1-periodic-wall-bf16_shifted_sr": 3.7e-03,
+    "3d-o2xo2xo2-periodic-wall-bf16_shifted_sr": 1.1e-03,
 }
 
 
@@ -100,7 +106,7 @@ def _axes():
                 out.append((2, ((n, even), (n, even)), "periodic", bcy))
     for n in range(2, 8):
         out.append((2, ((1, False), (n, False)), "periodic", "wall"))
-    for n in range(1, 8):
+    for n in range(1, 14):
         out.append((2, ((1, False), (n, True)), "periodic", "wall"))
     for lat in (((1, False),) * 3, ((2, False),) * 3, ((1, False), (2, False), (1, False)),
                 ((1, False), (3, False), (1, False)), ((1, False), (2, True), (1, False)),
