@@ -562,60 +562,76 @@ __device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, 
     });
 }
 
-// Populations of one node in registers, one FP32 value each.
-template <int LX, int LY>
+// Populations of one node in registers, one FP32 value each: the velocity
+// rows b >= B0 of the node, row b in v[b - B0] (all rows by default).
+template <int LX, int LY, int B0 = 0, int NB = Axis<LY>::Q>
 struct FloatRegs {
-    float (&v)[Axis<LY>::Q][Axis<LX>::Q];
+    float (&v)[NB][Axis<LX>::Q];
     template <int b, int a>
-    __device__ __forceinline__ float get() const { return v[b][a]; }
+    __device__ __forceinline__ float get() const { return v[b - B0][a]; }
     template <int b, int a>
-    __device__ __forceinline__ void put(float x) { v[b][a] = x; }
+    __device__ __forceinline__ void put(float x) { v[b - B0][a] = x; }
 };
 
 // Populations of one node in registers as BF16 pairs (two per 32-bit
 // register, population q in half q % 2 of register q / 2): half the register
 // footprint of FloatRegs, so twice the waves per SIMD.  put() rounds as the
-// storage does, so the stores are exact.
-template <int LX, int LY, int ST>
+// storage does, so the stores are exact.  With B0 > 0 the registers hold the
+// velocity rows from B0 on (q counted from row B0; the random bits of the
+// stochastic rounding stay those of the population's own index).
+template <int LX, int LY, int ST, int B0 = 0, int NPW = (Axis<LX>::Q * Axis<LY>::Q + 1) / 2>
 struct PackedRegs {
-    static constexpr int QX = Axis<LX>::Q, Q = QX * Axis<LY>::Q, NP = (Q + 1) / 2;
+    static constexpr int QX = Axis<LX>::Q, NP = NPW;
     uint32_t (&pk)[NP];
     uint32_t h;  // node hash for the stochastic rounding
     template <int b, int a>
     __device__ __forceinline__ float get() const
     {
-        constexpr int q = b * QX + a;
-        const uint32_t w = pk[q >> 1];
-        return __builtin_bit_cast(float, (q & 1) ? (w & 0xffff0000u) : (w << 16));
+        constexpr int ql = (b - B0) * QX + a;
+        const uint32_t w = pk[ql >> 1];
+        return __builtin_bit_cast(float, (ql & 1) ? (w & 0xffff0000u) : (w << 16));
     }
     template <int b, int a>
     __device__ __forceinline__ void put(float x)
     {
-        constexpr int q = b * QX + a;
+        constexpr int q = b * QX + a, ql = (b - B0) * QX + a;
         if constexpr (ST == ST_BF16SR) {
-            bf16x2_t hv = __builtin_bit_cast(bf16x2_t, pk[q >> 1]);
-            hv = __builtin_amdgcn_cvt_sr_bf16_f32(hv, x, rnd_of<q>(h), (q & 1) != 0);
-            pk[q >> 1] = __builtin_bit_cast(uint32_t, hv);
+            bf16x2_t hv = __builtin_bit_cast(bf16x2_t, pk[ql >> 1]);
+            hv = __builtin_amdgcn_cvt_sr_bf16_f32(hv, x, rnd_of<q>(h), (ql & 1) != 0);
+            pk[ql >> 1] = __builtin_bit_cast(uint32_t, hv);
         } else {
             const uint32_t bits = __builtin_bit_cast(unsigned short, (__bf16)x);
-            pk[q >> 1] = (q & 1) ? ((pk[q >> 1] & 0xffffu) | (bits << 16)) : ((pk[q >> 1] & 0xffff0000u) | bits);
+            pk[ql >> 1] = (ql & 1) ? ((pk[ql >> 1] & 0xffffu) | (bits << 16)) : ((pk[ql >> 1] & 0xffff0000u) | bits);
         }
     }
 };
 
-// Density, momentum and velocity from working values (the shift has unit
-// mass and no momentum).
-template <int LX, int LY, int ST, class Regs>
-__device__ __forceinline__ void density_velocity(const Regs &v, float &rho, float &jx, float &jy, float &ux, float &uy)
+// Lattices whose nodes the interior-row step splits over two waves (more
+// than 144 velocities: a whole node does not fit two waves' registers): the
+// first wave of a pair holds the velocity rows b < split_row, the second the
+// others, and the two exchange their partial moment sums.
+template <int LX, int LY, int ST>
+constexpr bool split_node()
 {
-    using L = Lat<LX, LY, ST>;
-    float r = 0.0f;
+    return Lat<LX, LY, ST>::Q > 144;
+}
+template <int LY>
+constexpr int split_row()
+{
+    return (Axis<LY>::Q + 1) / 2;
+}
+
+// Mass and momentum sums of the working values of velocity rows [B0, B1).
+template <int LX, int LY, int ST, int B0, int B1, class Regs>
+__device__ __forceinline__ void moment_sums(const Regs &v, float &r, float &jx, float &jy)
+{
+    r = 0.0f;
     jx = 0.0f;
     jy = 0.0f;
-    unroll<L::QY>([&](auto B) {
+    unroll_from<B0, B1>([&](auto B) {
         constexpr int b = B, cb = Axis<LY>::c(b);
         float rs = 0.0f, rx = 0.0f;
-        unroll<L::QX>([&](auto A) {
+        unroll<Axis<LX>::Q>([&](auto A) {
             constexpr int a = A, ca = Axis<LX>::c(a);
             const float f = v.template get<b, a>();
             rs += f;
@@ -625,10 +641,38 @@ __device__ __forceinline__ void density_velocity(const Regs &v, float &rho, floa
         jx += rx;
         if constexpr (cb != 0) jy = __builtin_fmaf((float)cb, rs, jy);
     });
-    rho = L::shifted ? kShift<LX, LY>.sum + r : r;
+}
+
+// Density and velocity from the sums (the shift has unit mass and no
+// momentum).
+template <int LX, int LY, int ST>
+__device__ __forceinline__ void finish_moments(float r, float jx, float jy, float &rho, float &ux, float &uy)
+{
+    rho = Lat<LX, LY, ST>::shifted ? kShift<LX, LY>.sum + r : r;
     const float inv = 1.0f / rho;
     ux = jx * inv;
     uy = jy * inv;
+}
+
+// Density, momentum and velocity from working values.  Split lattices sum
+// the two halves of the velocity rows separately and then add them, as the
+// two waves of the split step do, so that every path gives the same bits.
+template <int LX, int LY, int ST, class Regs>
+__device__ __forceinline__ void density_velocity(const Regs &v, float &rho, float &jx, float &jy, float &ux, float &uy)
+{
+    float r;
+    if constexpr (split_node<LX, LY, ST>()) {
+        constexpr int H = split_row<LY>();
+        float r0, x0, y0, r1, x1, y1;
+        moment_sums<LX, LY, ST, 0, H>(v, r0, x0, y0);
+        moment_sums<LX, LY, ST, H, Axis<LY>::Q>(v, r1, x1, y1);
+        r = r0 + r1;
+        jx = x0 + x1;
+        jy = y0 + y1;
+    } else {
+        moment_sums<LX, LY, ST, 0, Axis<LY>::Q>(v, r, jx, jy);
+    }
+    finish_moments<LX, LY, ST>(r, jx, jy, rho, ux, uy);
 }
 
 // Storages whose update draws random bits: stochastic rounding of the BF16
@@ -679,7 +723,7 @@ __device__ __forceinline__ float relax_update(float f, float om, float neq, floa
 // the slowest populations (mass: the rest population, or the symmetric set of
 // smallest |c| on axes without one) and of the c = +-1 populations among them
 // (momentum).
-template <int LX, int LY, int ST, class Regs>
+template <int LX, int LY, int ST, int B0 = 0, int B1 = Axis<LY>::Q, class Regs>
 __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, float jx, float jy, float ux, float uy,
                                         uint32_t h)
 {
@@ -718,7 +762,8 @@ __device__ __forceinline__ void collide(const KArgs &p, Regs &v, float rho, floa
     const float dm = (float)(sx * sy - (double)rho) * (1.0f / (nx_min * ny_min));
     const float hx = (float)(0.5 * (mx * sy - (double)jx)) * (1.0f / ny_min);
     const float hy = (float)(0.5 * (sx * my - (double)jy)) * (1.0f / nx_min);
-    unroll<L::QY>([&](auto B) {
+    // relax the rows [B0, B1) held (all of them unless the node is split)
+    unroll_from<B0, B1>([&](auto B) {
         constexpr int b = B, cb = Axis<LY>::c(b);
         constexpr bool ymin = (cb < 0 ? -cb : cb) == Axis<LY>::cmin;
         unroll<L::QX>([&](auto A) {
@@ -909,6 +954,89 @@ __device__ __forceinline__ int row_set_node(int i, int nx, int ny)
     }
 }
 
+// ------------------------------------------------ the split interior step
+// Interior rows of a split lattice (split_node, with walls): a block of 256
+// lanes steps 128 nodes, each by a pair of its waves (waves 2g and 2g + 1
+// for the 64 nodes of group g), the first holding the velocity rows [0, H),
+// the second [H, QY), H = split_row.  Each wave pulls, sums, relaxes and
+// stores only its rows, so a node's populations take half the registers and
+// twice the waves fit.  The partial sums of mass and momentum meet in LDS
+// and are added in the order density_velocity adds them (first half plus
+// second half): the node's arithmetic is bitwise that of the unsplit node
+// code, which the batched and wall-row launches run.
+constexpr int kSplitNodes = kBlock / 2;
+
+// Words of [B0, B1) packed two per register, counted from row B0.
+template <int LX, int LY, int BCX, int B0, int B1, int NP>
+__device__ __forceinline__ void load_packed_rows(const KArgs &p, rsrc_t rs, const XAddr<LX, 2, BCX> &xa, int y,
+                                                 uint32_t (&pk)[NP])
+{
+    constexpr int QX = Axis<LX>::Q;
+    unroll_from<B0, B1>([&](auto B) {
+        constexpr int b = B, cb = Axis<LY>::c(b);
+        const uint32_t rowb = row_bytes<2>(p, y - cb);
+        unroll<QX>([&](auto A) {
+            constexpr int a = A, q = b * QX + a, ql = (b - B0) * QX + a;
+            const uint32_t raw = (uint32_t)__builtin_bit_cast(
+                unsigned short,
+                __builtin_amdgcn_raw_buffer_load_b16(rs, xa.template src_lane<a>(rowb),
+                                                     (uint32_t)q * p.plane_bytes + XAddr<LX, 2, BCX>::template src_uniform<a>(), 0));
+            if constexpr ((ql & 1) == 0)
+                pk[ql >> 1] = raw;
+            else
+                pk[ql >> 1] |= raw << 16;
+        });
+    });
+}
+
+template <int LX, int LY, int B0, int B1, int NP>
+__device__ __forceinline__ void store_packed_rows(const KArgs &p, rsrc_t rd, uint32_t off, const uint32_t (&pk)[NP])
+{
+    constexpr int QX = Axis<LX>::Q;
+    unroll<(B1 - B0) * QX>([&](auto Ql) {
+        constexpr int ql = Ql, q = B0 * QX + ql;
+        const unsigned short half = (ql & 1) ? (unsigned short)(pk[ql >> 1] >> 16) : (unsigned short)pk[ql >> 1];
+        __builtin_amdgcn_raw_buffer_store_b16(half, rd, off, (uint32_t)q * p.plane_bytes, kStoreNT);
+    });
+}
+
+// FP32 working values of rows [B0, B1) in v[b - B0] (interior rows: no
+// emission, no wrap across walls).
+template <int LX, int LY, int ST, int BCX, int B0, int B1, int NB>
+__device__ __forceinline__ void pull_rows(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
+                                          float (&v)[NB][Axis<LX>::Q])
+{
+    constexpr int QX = Axis<LX>::Q, EB = Elem<ST>::bytes;
+    unroll_from<B0, B1>([&](auto B) {
+        constexpr int b = B, cb = Axis<LY>::c(b);
+        const uint32_t rowb = row_bytes<EB>(p, y - cb);
+        unroll<QX>([&](auto A) {
+            constexpr int a = A;
+            v[b - B0][a] = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)(b * QX + a) * p.plane_bytes);
+        });
+    });
+}
+
+template <int LX, int LY, int ST, int B0, int B1, int NB>
+__device__ __forceinline__ void store_rows(const KArgs &p, rsrc_t rd, uint32_t off, const float (&v)[NB][Axis<LX>::Q])
+{
+    constexpr int QX = Axis<LX>::Q;
+    unroll_from<B0, B1>([&](auto B) {
+        unroll<QX>([&](auto A) {
+            constexpr int a = A, b = B;
+            st<ST>(rd, off, (uint32_t)(b * QX + a) * p.plane_bytes, v[b - B0][a]);
+        });
+    });
+}
+
+// The first N words of w opaque to the compiler (see opaque_words).
+template <int N, int NP>
+__device__ __forceinline__ void opaque_first(uint32_t (&w)[NP])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(w[i]));
+}
+
 // Waves per SIMD asked of the register allocator by the single-lattice step
 // kernel: two for FP32 storages up to 121 velocities, which fit 256
 // registers without spills (left alone, the allocator took 256 registers and
@@ -916,14 +1044,24 @@ __device__ __forceinline__ int row_set_node(int i, int nx, int ny)
 // per SIMD, 18% slower); no request beyond, or for the 16-bit wall-row
 // launches.  (The same request spilled in the resident and three-dimensional
 // kernels, which are left alone.)
-template <int LX, int LY, int ST>
+template <int LX, int LY, int ST, int ROWS = ROWS_ALL>
 constexpr int step_waves()
 {
-    return Elem<ST>::bytes == 4 && Lat<LX, LY, ST>::Q <= 121 ? 2 : 1;
+    return Elem<ST>::bytes == 4 && Lat<LX, LY, ST>::Q <= 121 && ROWS != ROWS_WALLS ? 2 : 1;
+}
+
+// Whether the FP32 rows kernel also steps the wall rows (in its first
+// blocks): where the wall path fits its two-wave register budget, i.e. walls
+// reaching up to 25 rows; at 27 rows (the G-D1Q28 axis) the absorbed-mass
+// sums spilled, and the wall rows get a launch of their own.
+template <int LY>
+constexpr bool fp32_merged_walls()
+{
+    return Axis<LY>::vmax <= 25;
 }
 
 template <int LX, int LY, int ST, int BCX, int BCY, int ROWS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves<LX, LY, ST>()))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves<LX, LY, ST, ROWS>()))) void
 step_kernel(KArgs p)
 {
     const int i = row_set_node<LY, ROWS>(tile_index(p) * kBlock + (int)threadIdx.x, p.nx, p.ny);
@@ -998,6 +1136,89 @@ step_kernel_rows(KArgs p)
     const int i = row_set_node<LY, ROWS_INTERIOR>(tile_of(b, G, p.remap) * kBlock + (int)threadIdx.x, p.nx, p.ny);
     if (i < 0) return;
     step_node<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>(p, i, p.seed);
+}
+
+// The interior rows of a lattice with walls, split over wave pairs (see
+// kSplitNodes); the wall rows are a launch of their own (one node per lane in
+// FP32 registers with the wall sums: in the same kernel they would set its
+// register budget).  Two waves per SIMD are asked of the register allocator.
+template <int LX, int LY, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel_split(KArgs p)
+{
+    static_assert(BCX == BCX_WRAP && BCY == BCY_WALL, "the split step is built for channels in compact rows");
+    using L = Lat<LX, LY, ST>;
+    constexpr int QX = L::QX, QY = L::QY, H = split_row<LY>(), R = Axis<LY>::vmax;
+    __shared__ float xch[kBlock / 64][3][64];
+    const int b = blockIdx.x, G = gridDim.x;
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, half = wave & 1;
+    const int in = row_set_node<LY, ROWS_INTERIOR>(tile_of(b, G, p.remap) * kSplitNodes + (wave >> 1) * 64 + lane,
+                                                   p.nx, p.ny);
+    // lanes past the last node step the first interior node and store nothing
+    // (every wave must reach the barrier)
+    const bool valid = in >= 0;
+    const int i = valid ? in : R * p.nx;
+    const int y = i / p.nx, x = i - y * p.nx;
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
+    const uint32_t h = storage_hash<ST>(p.seed, i, y);
+    const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+    const uint32_t off = (uint32_t)(y * p.nxp + x) * (uint32_t)L::EB;
+    float r, jx, jy;
+    auto exchange = [&](float &R0, float &JX, float &JY) {
+        xch[wave][0][lane] = r;
+        xch[wave][1][lane] = jx;
+        xch[wave][2][lane] = jy;
+        __syncthreads();
+        const int w0 = wave & ~1, w1 = w0 | 1;  // first half + second half
+        R0 = xch[w0][0][lane] + xch[w1][0][lane];
+        JX = xch[w0][1][lane] + xch[w1][1][lane];
+        JY = xch[w0][2][lane] + xch[w1][2][lane];
+    };
+    float R0, JX, JY, rho, ux, uy;
+    if constexpr (L::EB == 2) {
+        constexpr int NP = (H * QX + 1) / 2;  // the larger half
+        uint32_t pk[NP];
+        if (half == 0) {
+            load_packed_rows<LX, LY, BCX, 0, H>(p, rs, xa, y, pk);
+            moment_sums<LX, LY, ST, 0, H>(PackedRegs<LX, LY, ST, 0, NP>{pk, h}, r, jx, jy);
+        } else {
+            load_packed_rows<LX, LY, BCX, H, QY>(p, rs, xa, y, pk);
+            moment_sums<LX, LY, ST, H, QY>(PackedRegs<LX, LY, ST, H, NP>{pk, h}, r, jx, jy);
+        }
+        exchange(R0, JX, JY);
+        finish_moments<LX, LY, ST>(R0, JX, JY, rho, ux, uy);
+        if (half == 0) {
+            if constexpr (ST == ST_BF16SR) opaque_first<(H * QX + 1) / 2>(pk);
+            PackedRegs<LX, LY, ST, 0, NP> regs{pk, h};
+            collide<LX, LY, ST, 0, H>(p, regs, rho, JX, JY, ux, uy, h);
+            if (valid) store_packed_rows<LX, LY, 0, H>(p, rd, off, pk);
+        } else {
+            if constexpr (ST == ST_BF16SR) opaque_first<((QY - H) * QX + 1) / 2>(pk);
+            PackedRegs<LX, LY, ST, H, NP> regs{pk, h};
+            collide<LX, LY, ST, H, QY>(p, regs, rho, JX, JY, ux, uy, h);
+            if (valid) store_packed_rows<LX, LY, H, QY>(p, rd, off, pk);
+        }
+    } else {
+        float v[H][QX];
+        if (half == 0) {
+            pull_rows<LX, LY, ST, BCX, 0, H>(p, rs, xa, y, v);
+            moment_sums<LX, LY, ST, 0, H>(FloatRegs<LX, LY, 0, H>{v}, r, jx, jy);
+        } else {
+            pull_rows<LX, LY, ST, BCX, H, QY>(p, rs, xa, y, v);
+            moment_sums<LX, LY, ST, H, QY>(FloatRegs<LX, LY, H, H>{v}, r, jx, jy);
+        }
+        exchange(R0, JX, JY);
+        finish_moments<LX, LY, ST>(R0, JX, JY, rho, ux, uy);
+        if (half == 0) {
+            FloatRegs<LX, LY, 0, H> regs{v};
+            collide<LX, LY, ST, 0, H>(p, regs, rho, JX, JY, ux, uy, mix32(h));
+            if (valid) store_rows<LX, LY, ST, 0, H>(p, rd, off, v);
+        } else {
+            FloatRegs<LX, LY, H, H> regs{v};
+            collide<LX, LY, ST, H, QY>(p, regs, rho, JX, JY, ux, uy, mix32(h));
+            if (valid) store_rows<LX, LY, ST, H, QY>(p, rd, off, v);
+        }
+    }
 }
 
 // Batched step: many lattices of one variant in one launch.  Block b takes

@@ -16,7 +16,17 @@ template <int LX, int LY, int ST, int BCX, int BCY>
 struct Launchers {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
-        if constexpr (Elem<ST>::bytes == 2 && BCY == BCY_WALL) {
+        if constexpr (BCY == BCY_WALL && BCX == BCX_WRAP && split_node<LX, LY, ST>()) {
+            // more than 144 velocities: the interior rows with each node split
+            // over a wave pair, then the rows next to the walls
+            constexpr int R = Axis<LY>::vmax;
+            const int interior = (a.ny - 2 * R) * a.nx, walls = 2 * R * a.nx;
+            if (interior > 0)
+                hipLaunchKernelGGL((step_kernel_split<LX, LY, ST, BCX, BCY>),
+                                   dim3((interior + kSplitNodes - 1) / kSplitNodes), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>), dim3((walls + kBlock - 1) / kBlock),
+                               dim3(kBlock), 0, s, a);
+        } else if constexpr (Elem<ST>::bytes == 2 && BCY == BCY_WALL) {
             // packed interior rows and the rows next to the walls: one launch
             // where both fit the packed kernel's registers, else two
             constexpr int R = Axis<LY>::vmax;  // rows next to each wall that take emission
@@ -43,13 +53,21 @@ struct Launchers {
             // node; 0.5-3.5% slower for shorter reach, which keeps it)
             constexpr int R = Axis<LY>::vmax;
             const int interior = (a.ny - 2 * R) * a.nx, walls = 2 * R * a.nx;
-            if (interior > 0)
-                hipLaunchKernelGGL((step_kernel_rows<LX, LY, ST, BCX, BCY, true>),
-                                   dim3(wall_blocks<LY>(a.nx) + (interior + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                                   s, a);
-            else
-                hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>),
-                                   dim3((walls + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+            if constexpr (fp32_merged_walls<LY>()) {
+                if (interior > 0)
+                    hipLaunchKernelGGL((step_kernel_rows<LX, LY, ST, BCX, BCY, true>),
+                                       dim3(wall_blocks<LY>(a.nx) + (interior + kBlock - 1) / kBlock), dim3(kBlock),
+                                       0, s, a);
+                else
+                    hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>),
+                                       dim3((walls + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+            } else {
+                if (interior > 0)
+                    hipLaunchKernelGGL((step_kernel_rows<LX, LY, ST, BCX, BCY, false>),
+                                       dim3((interior + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+                hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_WALLS>), dim3((walls + kBlock - 1) / kBlock),
+                                   dim3(kBlock), 0, s, a);
+            }
         } else {
             hipLaunchKernelGGL((step_kernel<LX, LY, ST, BCX, BCY, ROWS_ALL>), dim3(grid), dim3(kBlock), 0, s, a);
         }
