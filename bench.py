@@ -64,11 +64,21 @@ def run_gpu(level: int, nx: int, ny: int, storage: str, steps: int, warmup: int,
     from paper_1905_04597_amd import glbm
     from paper_1905_04597_amd import workloads as wl
 
-    w = wl.poiseuille(nx=nx, ny=ny, level=level, storage=storage)
-    if lattice == "even":
-        w.even_x = w.even_y = True
-    elif lattice == "mixed_even":
-        w.level_x, w.even_y = 1, True
+    def make(rows):
+        w = wl.poiseuille(nx=nx, ny=rows, level=level, storage=storage)
+        if lattice == "even":
+            w.even_x = w.even_y = True
+        elif lattice == "mixed_even":
+            w.level_x, w.even_y = 1, True
+        return w
+
+    w = make(ny)
+    # a population buffer stays below 4 GiB (32-bit offsets): G-D2Q256 in
+    # FP32 at 4096 x 1024 would need exactly 4 GiB, so it runs one row fewer
+    rows_max = ((1 << 32) - 1) // (w.nvel * ELEM_BYTES[storage] * nx)
+    if ny > rows_max:
+        ny = rows_max
+        w = make(ny)
     s = glbm.solver_for(w)
     s.init_fields()
     gpu_s, wall_s = time_steps(s, steps, warmup)
@@ -77,7 +87,7 @@ def run_gpu(level: int, nx: int, ny: int, storage: str, steps: int, warmup: int,
     per_step = gpu_s / steps
     algo_bytes = 2 * Q * ELEM_BYTES[storage] * nodes
     out = {
-        "level": level, "k": level - 1, "Q": Q, "glups": nodes * steps / gpu_s / 1e9,
+        "level": level, "k": level - 1, "Q": Q, "ny": ny, "glups": nodes * steps / gpu_s / 1e9,
         "ms_per_step": per_step * 1e3, "achieved_GBs": algo_bytes / per_step / 1e9,
         "bytes_per_launch": algo_bytes, "wall_s": wall_s,
     }
@@ -85,6 +95,13 @@ def run_gpu(level: int, nx: int, ny: int, storage: str, steps: int, warmup: int,
     out["mass_drift_rel"] = abs(st["mass"] - nodes) / nodes
     s.close()
     return out
+
+
+# Three-dimensional sweep lines: D3Q27, G-D3Q125, G-D3Q343 and the channels
+# D1Q3 x G-D1Q(2N+1) x D1Q3 and D1Q3 x G-D1Q(2N+2) x D1Q3, N = 2..7.
+SWEEP_3D = [((1, 1, 1), False, (256, 256, 128)), ((2, 2, 2), False, (128, 128, 128)),
+            ((3, 3, 3), False, (128, 128, 128))] + [
+    ((1, n, 1), ev, (256, 128, 128)) for ev in (False, True) for n in range(2, 8)]
 
 
 def run_gpu3(levels, even_y: bool, nx: int, ny: int, nz: int, storage: str, steps: int, warmup: int):
@@ -444,8 +461,7 @@ def main(argv=None):
         print(json.dumps(run_solves()), flush=True)
         return 0
     if a.only_3d:
-        for levels, ev, shape in (((1, 1, 1), False, (256, 256, 128)), ((2, 2, 2), False, (128, 128, 128)),
-                                  ((1, 3, 1), False, (256, 128, 128)), ((1, 3, 1), True, (256, 128, 128))):
+        for levels, ev, shape in SWEEP_3D:
             print(json.dumps(run_gpu3(levels, ev, *shape, a.storage, a.sweep_steps, 5)), flush=True)
         return 0
     if a.batched_only:
@@ -465,15 +481,16 @@ def main(argv=None):
             sweep[-1]["frac"] = round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)
         # the G-D1Q(2N+2) lattices: D1Q3 x G-D1Q(2N+2) channels and the
         # symmetric products
-        for lattice, levels in (("mixed_even", range(1, 14)), ("even", range(1, 7))):
+        for lattice, levels in (("mixed_even", range(1, 14)), ("even", range(1, 8))):
             for lv in levels:
                 r = run_gpu(lv, a.nx, a.ny, a.storage, a.sweep_steps, 5, lattice)
                 sweep.append({"lattice": lattice, "N": lv, "Q": r["Q"], "glups": round(r["glups"], 4),
                               "achieved_GBs": round(r["achieved_GBs"], 4), "ms_per_step": round(r["ms_per_step"], 4),
                               "frac": round(r["achieved_GBs"] / PEAK_HBM_GBS, 4)})
-        # three dimensions: D3Q27, G-D3Q125, D1Q3 x G-D1Q7 (or Q8) x D1Q3
-        for levels, ev, shape in (((1, 1, 1), False, (256, 256, 128)), ((2, 2, 2), False, (128, 128, 128)),
-                                  ((1, 3, 1), False, (256, 128, 128)), ((1, 3, 1), True, (256, 128, 128))):
+                if r["ny"] != a.ny:
+                    sweep[-1]["ny"] = r["ny"]
+        # three dimensions
+        for levels, ev, shape in SWEEP_3D:
             sweep.append(run_gpu3(levels, ev, *shape, a.storage, a.sweep_steps, 5))
         # the 16-bit storages over the 2N+1 levels (same lattice and size)
         for st in ("bf16_shifted_sr",):

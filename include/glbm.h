@@ -92,7 +92,7 @@ extern "C" {
                             Built: one dimension (N = 1..7), the mixed lattices
                             G-D1Q3 x G-D1Q(2N+2) with walls across the even axis (the form of
                             sections 5.3-5.4, N = 1..13) and the symmetric two-dimensional
-                            products (N = 1..6). */
+                            products (N = 1..7). */
 
 typedef struct glbm_config {
     int32_t dims;     /* 1, 2 or 3 */
@@ -113,9 +113,10 @@ typedef struct glbm_config {
     int32_t kind_y;   /* GLBM_AXIS_ODD or GLBM_AXIS_EVEN (two dimensions); ignored in 1D */
     /* Three dimensions (dims = 3): the tensor product of three axes (section 4
      * with a third factor), periodic in x and z, periodic or walls in y.
-     * Built: D3Q27 (levels 1,1,1), G-D3Q125 (2,2,2), D1Q3 x G-D1Q(2N+1) x D1Q3
-     * (1,N,1, N = 2, 3) and D1Q3 x G-D1Q(2N+2) x D1Q3 (1,N,1 with kind_y EVEN,
-     * N = 2, 3).  Ignored in one and two dimensions. */
+     * Built: D3Q27 (levels 1,1,1), G-D3Q125 (2,2,2), G-D3Q343 (3,3,3),
+     * D1Q3 x G-D1Q(2N+1) x D1Q3 (1,N,1, N = 2..7) and D1Q3 x G-D1Q(2N+2) x D1Q3
+     * (1,N,1 with kind_y EVEN, N = 2..7).  Batches take every one of them but
+     * G-D3Q343.  Ignored in one and two dimensions. */
     int64_t nz;       /* nodes along z (>= the fastest z velocity) */
     int32_t level_z;  /* level of the z axis, 1..GLBM_MAX_LEVEL */
     int32_t kind_z;   /* GLBM_AXIS_ODD or GLBM_AXIS_EVEN */
@@ -242,8 +243,8 @@ int glbm_destroy(glbm_t *h);
 const char *glbm_last_error(void);
 
 /* ------------------------------------------------------------------------
- * Batched stepping: many solvers advanced together (uneven sizes, levels and
- * parameters).  Members of the same kernel variant (levels, storage,
+ * Batched stepping: many solvers advanced together (uneven sizes, levels,
+ * dimensions and parameters).  Members of the same kernel variant (levels, storage,
  * boundaries) share one launch per step over a table of tiles, each tile a
  * run of nodes of one member; a chunk of steps is captured once into a HIP
  * graph and replayed.  Every node runs exactly the code of glbm_step, so a
@@ -260,9 +261,11 @@ typedef struct glbm_batch_options {
     int32_t tile_nodes;  /* nodes per workgroup: 64, 128 or 256 (0 = 256) */
     int32_t order;       /* GLBM_ORDER_* */
     int32_t graph_steps; /* steps per captured HIP graph; 0 = plain launches */
-    int32_t resident_nodes; /* members of at most this many nodes are stepped by one
-                               workgroup each, all steps of a chunk in one launch per
-                               variant (small lattices: no launch per step); 0 = none */
+    int32_t resident_nodes; /* one- and two-dimensional members of at most this many
+                               nodes are stepped by one workgroup each, all steps of a
+                               chunk in one launch per variant (small lattices: no
+                               launch per step); 0 = none.  Three-dimensional members
+                               are always tiled. */
     int32_t streams;     /* kernel variants advance side by side on up to this many
                             streams (1..8; 0 = 1): the batch's stream and streams - 1
                             more that the batch creates (default priority), joined

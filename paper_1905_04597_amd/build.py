@@ -66,18 +66,21 @@ def _compile(args):
 def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     # the three-dimensional objects are among the slowest: start them first
-    tasks = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3.o"), [])]
+    tasks = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3_%d.o" % k), ["-DGLBM_3D_PART=%d" % k])
+             for k in (8, 7, 6, 5, 4, 0, 1, 2, 3)]
     tasks.append((os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), []))
     tasks.append((os.path.join(CSRC, "glbm_probe.hip"), os.path.join(BUILD, "glbm_probe.o"), []))
     for lv in LEVELS:
         for even in (0, 1):
-            for compact in (0, 1):
-                if lv == 0 and not compact:
-                    continue  # the mixed lattices are two-dimensional only
+            # one-dimensional; two-dimensional periodic y (or mixed); symmetric with walls
+            for compact, walls in ((0, 0), (1, 0), (1, 1)):
+                if lv == 0 and (not compact or walls):
+                    continue  # the mixed lattices: two-dimensional, one object
                 tasks.append((os.path.join(CSRC, "glbm_inst.hip"),
                               os.path.join(BUILD, "glbm_inst_%s%d%s.o" % ("e" if even else "", lv,
-                                                                         "c" if compact else "")),
-                              ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_EVEN=%d" % even, "-DGLBM_COMPACT=%d" % compact]))
+                                                                         ("cw" if walls else "c") if compact else "")),
+                              ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_EVEN=%d" % even, "-DGLBM_COMPACT=%d" % compact,
+                               "-DGLBM_WALLS=%d" % walls]))
     # levels 8..13: the mixed channel lattice D1Q3 x G-D1Q(2N+2) only
     for lv in MIXED_LEVELS:
         tasks.insert(2, (os.path.join(CSRC, "glbm_inst.hip"), os.path.join(BUILD, "glbm_inst_e%dc.o" % lv),

@@ -48,7 +48,9 @@ void register_all()
 #define GLBM_CALL_REGISTER(E, C, L) register_##E##_##C##_##L();
     GLBM_OBJECTS(GLBM_CALL_REGISTER)
 #undef GLBM_CALL_REGISTER
-    register3();
+#define GLBM_CALL_REGISTER3(K) register3_##K();
+    GLBM_OBJECTS3(GLBM_CALL_REGISTER3)
+#undef GLBM_CALL_REGISTER3
 }
 
 // Host copy of the per-axis equilibrium at rho = 1 (N-fold convolution of the
@@ -723,7 +725,7 @@ static int check_members(glbm_t *const *members, int32_t n, const glbm_batch *se
         glbm_solver *m = members[i];
         if (!m) return fail(GLBM_ERR_INVALID, "member %d is NULL", i);
         if (!m->ready) return fail(GLBM_ERR_STATE, "member %d is not initialised", i);
-        if (!m->var->batch) return fail(GLBM_ERR_UNSUPPORTED, "member %d: batches take one- and two-dimensional lattices", i);
+        if (!m->var->batch) return fail(GLBM_ERR_UNSUPPORTED, "member %d: its lattice has no batched step", i);
         const bool mine = self && std::find(self->members.begin(), self->members.end(), m) != self->members.end();
         if (m->in_batch && !mine) return fail(GLBM_ERR_STATE, "member %d already belongs to a batch", i);
         for (int j = 0; j < i; ++j)
@@ -744,7 +746,8 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
     };
     const int tile = b->opt.tile_nodes;
     auto is_resident = [&](const glbm_solver *m) {
-        return b->opt.resident_nodes > 0 && m->geo.nx * m->geo.ny <= (int64_t)b->opt.resident_nodes;
+        return b->opt.resident_nodes > 0 && m->var->resident &&
+               m->geo.nx * m->geo.ny * m->geo.nz <= (int64_t)b->opt.resident_nodes;
     };
     std::vector<const Variant *> vars;
     for (int i = 0; i < n; ++i)
@@ -773,7 +776,8 @@ static int plan(glbm_batch *b, glbm_t *const *members, int32_t n)
                 const glbm_solver *m = members[i];
                 if (m->var != v || is_resident(m)) continue;
                 const int64_t nx = m->geo.nx, ny = m->geo.ny, ly = m->geo.y.vmax;  // rows with wall emission
-                const int64_t cnt = rows == ROWS_ALL ? nx * ny : rows == ROWS_INTERIOR ? (ny - 2 * ly) * nx : 2 * ly * nx;
+                const int64_t cnt = rows == ROWS_ALL ? nx * ny * m->geo.nz
+                                    : rows == ROWS_INTERIOR ? (ny - 2 * ly) * nx : 2 * ly * nx;
                 if (cnt > 0) parts.push_back({i, (int)cnt, (double)cnt * m->geo.q});
             }
             if (b->opt.order == GLBM_ORDER_LARGEST_FIRST)

@@ -832,7 +832,9 @@ __device__ __forceinline__ uint32_t storage_hash(uint32_t seed, int i, int y)
 }
 
 // Seed of the stochastic rounding for the step that produces time t (host and
-// device: a batched lattice draws the same bits as the lattice alone).
+// device: a batched lattice draws the same bits as the lattice alone): a
+// golden-ratio Weyl step followed by the first two xor-shift-multiply rounds
+// of the splitmix64 finaliser (Steele, Lea and Flood, 2014).
 __host__ __device__ inline uint32_t step_seed(int64_t t)
 {
     uint64_t x = (uint64_t)t * 0x9e3779b97f4a7c15ULL + 0x632be59bd9b4e019ULL;
@@ -955,8 +957,9 @@ __device__ __forceinline__ int row_set_node(int i, int nx, int ny)
 }
 
 // ------------------------------------------------ the split interior step
-// Interior rows of a split lattice (split_node, with walls): a block of 256
-// lanes steps 128 nodes, each by a pair of its waves (waves 2g and 2g + 1
+// The nodes of a split lattice (split_node) in compact rows, all of them
+// with a periodic y, the interior rows with walls: a block of 256 lanes steps
+// 128 nodes, each by a pair of its waves (waves 2g and 2g + 1
 // for the 64 nodes of group g), the first holding the velocity rows [0, H),
 // the second [H, QY), H = split_row.  Each wave pulls, sums, relaxes and
 // stores only its rows, so a node's populations take half the registers and
@@ -966,15 +969,29 @@ __device__ __forceinline__ int row_set_node(int i, int nx, int ny)
 // code, which the batched and wall-row launches run.
 constexpr int kSplitNodes = kBlock / 2;
 
+// Row that velocity row b of row y pulls from: y - c_b, wrapped across a
+// periodic y (the rows reached stay within one period); with walls the split
+// step takes only interior rows, whose sources lie inside.
+template <int LY, int BCY, int cb>
+__device__ __forceinline__ int source_row(int y, int ny)
+{
+    int ys = y - cb;
+    if constexpr (BCY == BCY_PERIODIC) {
+        if constexpr (cb > 0) ys = ys < 0 ? ys + ny : ys;
+        if constexpr (cb < 0) ys = ys >= ny ? ys - ny : ys;
+    }
+    return ys;
+}
+
 // Words of [B0, B1) packed two per register, counted from row B0.
-template <int LX, int LY, int BCX, int B0, int B1, int NP>
+template <int LX, int LY, int BCX, int BCY, int B0, int B1, int NP>
 __device__ __forceinline__ void load_packed_rows(const KArgs &p, rsrc_t rs, const XAddr<LX, 2, BCX> &xa, int y,
                                                  uint32_t (&pk)[NP])
 {
     constexpr int QX = Axis<LX>::Q;
     unroll_from<B0, B1>([&](auto B) {
         constexpr int b = B, cb = Axis<LY>::c(b);
-        const uint32_t rowb = row_bytes<2>(p, y - cb);
+        const uint32_t rowb = row_bytes<2>(p, source_row<LY, BCY, cb>(y, p.ny));
         unroll<QX>([&](auto A) {
             constexpr int a = A, q = b * QX + a, ql = (b - B0) * QX + a;
             const uint32_t raw = (uint32_t)__builtin_bit_cast(
@@ -1000,16 +1017,16 @@ __device__ __forceinline__ void store_packed_rows(const KArgs &p, rsrc_t rd, uin
     });
 }
 
-// FP32 working values of rows [B0, B1) in v[b - B0] (interior rows: no
-// emission, no wrap across walls).
-template <int LX, int LY, int ST, int BCX, int B0, int B1, int NB>
+// FP32 working values of rows [B0, B1) in v[b - B0] (no wall emission: a
+// periodic y, or the interior rows of a channel).
+template <int LX, int LY, int ST, int BCX, int BCY, int B0, int B1, int NB>
 __device__ __forceinline__ void pull_rows(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
                                           float (&v)[NB][Axis<LX>::Q])
 {
     constexpr int QX = Axis<LX>::Q, EB = Elem<ST>::bytes;
     unroll_from<B0, B1>([&](auto B) {
         constexpr int b = B, cb = Axis<LY>::c(b);
-        const uint32_t rowb = row_bytes<EB>(p, y - cb);
+        const uint32_t rowb = row_bytes<EB>(p, source_row<LY, BCY, cb>(y, p.ny));
         unroll<QX>([&](auto A) {
             constexpr int a = A;
             v[b - B0][a] = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)(b * QX + a) * p.plane_bytes);
@@ -1138,25 +1155,26 @@ step_kernel_rows(KArgs p)
     step_node<LX, LY, ST, BCX, BCY, ROWS_INTERIOR>(p, i, p.seed);
 }
 
-// The interior rows of a lattice with walls, split over wave pairs (see
-// kSplitNodes); the wall rows are a launch of their own (one node per lane in
-// FP32 registers with the wall sums: in the same kernel they would set its
-// register budget).  Two waves per SIMD are asked of the register allocator.
+// Nodes of a split lattice over wave pairs (see kSplitNodes): every node
+// with a periodic y; the interior rows with walls, whose wall rows are a
+// launch of their own (one node per lane in FP32 registers with the wall
+// sums: in the same kernel they would set its register budget).  Two waves
+// per SIMD are asked of the register allocator.
 template <int LX, int LY, int ST, int BCX, int BCY>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel_split(KArgs p)
 {
-    static_assert(BCX == BCX_WRAP && BCY == BCY_WALL, "the split step is built for channels in compact rows");
+    static_assert(BCX == BCX_WRAP, "the split step is built for compact rows");
     using L = Lat<LX, LY, ST>;
     constexpr int QX = L::QX, QY = L::QY, H = split_row<LY>(), R = Axis<LY>::vmax;
+    constexpr int ROWS = BCY == BCY_WALL ? ROWS_INTERIOR : ROWS_ALL;
     __shared__ float xch[kBlock / 64][3][64];
     const int b = blockIdx.x, G = gridDim.x;
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, half = wave & 1;
-    const int in = row_set_node<LY, ROWS_INTERIOR>(tile_of(b, G, p.remap) * kSplitNodes + (wave >> 1) * 64 + lane,
-                                                   p.nx, p.ny);
-    // lanes past the last node step the first interior node and store nothing
-    // (every wave must reach the barrier)
+    const int in = row_set_node<LY, ROWS>(tile_of(b, G, p.remap) * kSplitNodes + (wave >> 1) * 64 + lane, p.nx, p.ny);
+    // lanes past the last node step the first node of the row set and store
+    // nothing (every wave must reach the barrier)
     const bool valid = in >= 0;
-    const int i = valid ? in : R * p.nx;
+    const int i = valid ? in : (BCY == BCY_WALL ? R * p.nx : 0);
     const int y = i / p.nx, x = i - y * p.nx;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
@@ -1179,10 +1197,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         constexpr int NP = (H * QX + 1) / 2;  // the larger half
         uint32_t pk[NP];
         if (half == 0) {
-            load_packed_rows<LX, LY, BCX, 0, H>(p, rs, xa, y, pk);
+            load_packed_rows<LX, LY, BCX, BCY, 0, H>(p, rs, xa, y, pk);
             moment_sums<LX, LY, ST, 0, H>(PackedRegs<LX, LY, ST, 0, NP>{pk, h}, r, jx, jy);
         } else {
-            load_packed_rows<LX, LY, BCX, H, QY>(p, rs, xa, y, pk);
+            load_packed_rows<LX, LY, BCX, BCY, H, QY>(p, rs, xa, y, pk);
             moment_sums<LX, LY, ST, H, QY>(PackedRegs<LX, LY, ST, H, NP>{pk, h}, r, jx, jy);
         }
         exchange(R0, JX, JY);
@@ -1201,10 +1219,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     } else {
         float v[H][QX];
         if (half == 0) {
-            pull_rows<LX, LY, ST, BCX, 0, H>(p, rs, xa, y, v);
+            pull_rows<LX, LY, ST, BCX, BCY, 0, H>(p, rs, xa, y, v);
             moment_sums<LX, LY, ST, 0, H>(FloatRegs<LX, LY, 0, H>{v}, r, jx, jy);
         } else {
-            pull_rows<LX, LY, ST, BCX, H, QY>(p, rs, xa, y, v);
+            pull_rows<LX, LY, ST, BCX, BCY, H, QY>(p, rs, xa, y, v);
             moment_sums<LX, LY, ST, H, QY>(FloatRegs<LX, LY, H, H>{v}, r, jx, jy);
         }
         exchange(R0, JX, JY);

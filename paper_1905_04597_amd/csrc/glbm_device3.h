@@ -131,16 +131,14 @@ __device__ __forceinline__ float wall_absorbed3(const KArgs &p, rsrc_t rs, const
     return s;
 }
 
-// Pre-collision populations of node (x, y, z): pulled, or emitted by a wall.
-// INTERIOR: the node is at least the fastest y velocity away from both walls,
-// so nothing is emitted into it and the pull has no branches (all its loads
-// can be in flight together).
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR = false>
-__device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y, int z,
-                                      float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q])
+// Wall re-emission factors of a node in row y: rho_w / (J+ sum_a fw_a) for
+// the bottom and top walls (zero out of their reach; INTERIOR: none).
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
+__device__ __forceinline__ void wall_rates3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
+                                            int z, float (&rw)[2])
 {
-    using L = Lat3<LX, LY, LZ, ST>;
-    float rw[2] = {0.0f, 0.0f};
+    rw[0] = 0.0f;
+    rw[1] = 0.0f;
     if constexpr (BCY == BCY_WALL && !INTERIOR) {
         constexpr double jp = kYZ<LY, LZ>.jplus;
         constexpr int reach = Axis<LY>::vmax;
@@ -148,111 +146,161 @@ __device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX,
         if (y >= p.ny - reach)
             rw[1] = wall_absorbed3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z, nullptr) / (float)(jp * p.fwsum[1]);
     }
-    unroll<L::QZ>([&](auto C) {
-        constexpr int c = C, cc = Axis<LZ>::c(c);
-        const int zs = wrap_z<LZ>(z - cc, p.nz);
-        unroll<L::QY>([&](auto B) {
-            constexpr int b = B, cb = Axis<LY>::c(b);
-            int ys = y - cb;
-            bool emit = false;
-            if constexpr (BCY == BCY_WALL) {
-                if constexpr (cb > 0 && !INTERIOR) emit = ys < 0;
-                if constexpr (cb < 0 && !INTERIOR) emit = ys >= p.ny;
-            } else {
-                if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
-                if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
-            }
-            if (emit) {
-                constexpr int side = cb > 0 ? 0 : 1;
-                const float rwb = rw[side] * kYZ<LY, LZ>.w[c][b];
-                unroll<L::QX>([&](auto A) {
-                    constexpr int a = A;
-                    if constexpr (L::shifted)
-                        v[c][b][a] = __builtin_fmaf(rwb, p.fw[side][a], -kShift3<LX, LY, LZ>.s[c][b][a]);
-                    else
-                        v[c][b][a] = rwb * p.fw[side][a];
-                });
-            } else {
-                const uint32_t rowb = row_bytes<L::EB>(p, zs * p.ny + ys);
-                unroll<L::QX>([&](auto A) {
-                    constexpr int a = A;
-                    v[c][b][a] = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)L::template q<a, b, c>() * p.plane_bytes);
-                });
-            }
+}
+
+// Pre-collision populations of velocity row (b, c) of node (x, y, z):
+// pulled, or emitted by a wall (rw from wall_rates3).  INTERIOR: the node is
+// at least the fastest y velocity away from both walls, so nothing is emitted
+// into it and the pull has no branches (all its loads can be in flight
+// together).
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR, int b, int c>
+__device__ __forceinline__ void pull3_row(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
+                                          int z, const float (&rw)[2], float (&row)[Axis<LX>::Q])
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    constexpr int cb = Axis<LY>::c(b), cc = Axis<LZ>::c(c);
+    const int zs = wrap_z<LZ>(z - cc, p.nz);
+    int ys = y - cb;
+    bool emit = false;
+    if constexpr (BCY == BCY_WALL) {
+        if constexpr (cb > 0 && !INTERIOR) emit = ys < 0;
+        if constexpr (cb < 0 && !INTERIOR) emit = ys >= p.ny;
+    } else {
+        if constexpr (cb > 0) ys = ys < 0 ? ys + p.ny : ys;
+        if constexpr (cb < 0) ys = ys >= p.ny ? ys - p.ny : ys;
+    }
+    if (emit) {
+        constexpr int side = cb > 0 ? 0 : 1;
+        const float rwb = rw[side] * kYZ<LY, LZ>.w[c][b];
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A;
+            if constexpr (L::shifted)
+                row[a] = __builtin_fmaf(rwb, p.fw[side][a], -kShift3<LX, LY, LZ>.s[c][b][a]);
+            else
+                row[a] = rwb * p.fw[side][a];
+        });
+    } else {
+        const uint32_t rowb = row_bytes<L::EB>(p, zs * p.ny + ys);
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A;
+            row[a] = ld<ST>(rs, xa.template src<a>(rowb), (uint32_t)L::template q<a, b, c>() * p.plane_bytes);
+        });
+    }
+}
+
+// Pre-collision populations of node (x, y, z): pulled, or emitted by a wall.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR = false>
+__device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y, int z,
+                                      float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q])
+{
+    float rw[2];
+    wall_rates3<LX, LY, LZ, ST, BCX, BCY, INTERIOR>(p, rs, xa, y, z, rw);
+    unroll<Axis<LZ>::Q>([&](auto C) {
+        unroll<Axis<LY>::Q>([&](auto B) {
+            pull3_row<LX, LY, LZ, ST, BCX, BCY, INTERIOR, (int)B, (int)C>(p, rs, xa, y, z, rw, v[C][B]);
         });
     });
 }
 
-// BGK collision with the linear force (section 5.4) on FP32 working values,
-// with the conservative defect correction of the two-dimensional collide:
-// the FP32 tables rho F_a and F_b F_c carry the mass and momentum only up to
-// rounding; the exact (FP64) sums give the defect, which the slowest
-// populations take out.
-template <int LX, int LY, int LZ, int ST>
-__device__ __forceinline__ void collide3(const KArgs &p, float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q], float rho,
-                                         float jx, float jy, float jz, float ux, float uy, float uz, uint32_t h)
+// Equilibrium factors of a collision: rho F_a(u_x) and the force shape per x
+// velocity, F_b(u_y) F_c(u_z) of the velocity rows [R0, R1) (row r = c QY + b),
+// and the conservative defect correction: the FP32 tables rho F_a and F_b F_c
+// carry the mass and momentum only up to rounding; the exact (FP64) sums over
+// every row give the defect, which the slowest populations take out.
+template <int LX, int LY, int LZ, int R0, int R1>
+struct Eq3 {
+    float rF[Axis<LX>::Q], gK[Axis<LX>::Q], FYZ[R1 - R0];
+    float dm, hx, hy, hz;
+};
+
+template <int LX, int LY, int LZ, int R0, int R1>
+__device__ __forceinline__ void eq3_factors(const KArgs &p, float rho, float jx, float jy, float jz, float ux, float uy,
+                                            float uz, Eq3<LX, LY, LZ, R0, R1> &e)
 {
-    using L = Lat3<LX, LY, LZ, ST>;
-    const float om = p.omega;
-    float rF[L::QX], gK[L::QX], FYZ[L::QZ][L::QY];
+    constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q, QZ = Axis<LZ>::Q;
     double sx = 0.0, mx = 0.0, syz = 0.0, my = 0.0, mz = 0.0;
     {
-        double Fd[L::QX];
+        double Fd[QX];
         axis_equilibrium<LX, double>((double)ux, Fd);
-        unroll<L::QX>([&](auto A) {
+        unroll<QX>([&](auto A) {
             constexpr int a = A, ca = Axis<LX>::c(a);
-            rF[a] = (float)((double)rho * Fd[a]);
-            sx += (double)rF[a];
-            mx += (double)ca * (double)rF[a];
-            gK[a] = p.gth * (float)(kRest<LX>.w[a] * ca);
+            e.rF[a] = (float)((double)rho * Fd[a]);
+            sx += (double)e.rF[a];
+            mx += (double)ca * (double)e.rF[a];
+            e.gK[a] = p.gth * (float)(kRest<LX>.w[a] * ca);
         });
     }
     {
-        double Fy[L::QY], Fz[L::QZ];
+        double Fy[QY], Fz[QZ];
         axis_equilibrium<LY, double>((double)uy, Fy);
         axis_equilibrium<LZ, double>((double)uz, Fz);
-        unroll<L::QZ>([&](auto C) {
+        unroll<QZ>([&](auto C) {
             constexpr int c = C, cc = Axis<LZ>::c(c);
-            unroll<L::QY>([&](auto B) {
-                constexpr int b = B, cb = Axis<LY>::c(b);
-                FYZ[c][b] = (float)(Fy[b] * Fz[c]);
-                syz += (double)FYZ[c][b];
-                my += (double)cb * (double)FYZ[c][b];
-                mz += (double)cc * (double)FYZ[c][b];
+            unroll<QY>([&](auto B) {
+                constexpr int b = B, cb = Axis<LY>::c(b), r = c * QY + b;
+                const float fyz = (float)(Fy[b] * Fz[c]);
+                if constexpr (r >= R0 && r < R1) e.FYZ[r - R0] = fyz;
+                syz += (double)fyz;
+                my += (double)cb * (double)fyz;
+                mz += (double)cc * (double)fyz;
             });
         });
     }
     constexpr int nxm = Axis<LX>::cmin ? 2 : 1, nym = Axis<LY>::cmin ? 2 : 1, nzm = Axis<LZ>::cmin ? 2 : 1;
-    const float dm = (float)(sx * syz - (double)rho) * (1.0f / (nxm * nym * nzm));
-    const float hx = (float)(0.5 * (mx * syz - (double)jx)) * (1.0f / (nym * nzm));
-    const float hy = (float)(0.5 * (sx * my - (double)jy)) * (1.0f / (nxm * nzm));
-    const float hz = (float)(0.5 * (sx * mz - (double)jz)) * (1.0f / (nxm * nym));
-    unroll<L::QZ>([&](auto C) {
-        constexpr int c = C, cc = Axis<LZ>::c(c);
+    e.dm = (float)(sx * syz - (double)rho) * (1.0f / (nxm * nym * nzm));
+    e.hx = (float)(0.5 * (mx * syz - (double)jx)) * (1.0f / (nym * nzm));
+    e.hy = (float)(0.5 * (sx * my - (double)jy)) * (1.0f / (nxm * nzm));
+    e.hz = (float)(0.5 * (sx * mz - (double)jz)) * (1.0f / (nxm * nym));
+}
+
+// BGK relaxation with the linear force (section 5.4) of the velocity rows
+// [R0, R1); at(r, a) is the FP32 working value of population (a, row r).
+template <int LX, int LY, int LZ, int ST, int R0, int R1, class At>
+__device__ __forceinline__ void relax3_rows(const KArgs &p, const Eq3<LX, LY, LZ, R0, R1> &e, At &&at, uint32_t h)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    const float om = p.omega;
+    unroll_from<R0, R1>([&](auto Rr) {
+        constexpr int r = Rr, c = r / L::QY, b = r % L::QY, cc = Axis<LZ>::c(c), cb = Axis<LY>::c(b);
         constexpr bool zmin = (cc < 0 ? -cc : cc) == Axis<LZ>::cmin;
-        unroll<L::QY>([&](auto B) {
-            constexpr int b = B, cb = Axis<LY>::c(b);
-            constexpr bool ymin = (cb < 0 ? -cb : cb) == Axis<LY>::cmin;
-            unroll<L::QX>([&](auto A) {
-                constexpr int a = A, ca = Axis<LX>::c(a);
-                constexpr bool xmin = (ca < 0 ? -ca : ca) == Axis<LX>::cmin;
-                const float f = v[c][b][a];
-                float neq;  // f^eq - f
-                if constexpr (L::shifted)
-                    neq = __builtin_fmaf(rF[a], FYZ[c][b], -kShift3<LX, LY, LZ>.s[c][b][a]) - f;
-                else
-                    neq = __builtin_fmaf(rF[a], FYZ[c][b], -f);
-                if constexpr (xmin && ymin && zmin) neq -= dm;
-                if constexpr (ymin && zmin && ca == 1) neq -= hx;
-                if constexpr (ymin && zmin && ca == -1) neq += hx;
-                if constexpr (xmin && zmin && cb == 1) neq -= hy;
-                if constexpr (xmin && zmin && cb == -1) neq += hy;
-                if constexpr (xmin && ymin && cc == 1) neq -= hz;
-                if constexpr (xmin && ymin && cc == -1) neq += hz;
-                v[c][b][a] = relax_update<ST, L::template q<a, b, c>()>(f, om, neq, gK[a], kYZ<LY, LZ>.w[c][b], h);
-            });
+        constexpr bool ymin = (cb < 0 ? -cb : cb) == Axis<LY>::cmin;
+        unroll<L::QX>([&](auto A) {
+            constexpr int a = A, ca = Axis<LX>::c(a);
+            constexpr bool xmin = (ca < 0 ? -ca : ca) == Axis<LX>::cmin;
+            float &v = at(Rr, A);
+            const float f = v;
+            float neq;  // f^eq - f
+            if constexpr (L::shifted)
+                neq = __builtin_fmaf(e.rF[a], e.FYZ[r - R0], -kShift3<LX, LY, LZ>.s[c][b][a]) - f;
+            else
+                neq = __builtin_fmaf(e.rF[a], e.FYZ[r - R0], -f);
+            if constexpr (xmin && ymin && zmin) neq -= e.dm;
+            if constexpr (ymin && zmin && ca == 1) neq -= e.hx;
+            if constexpr (ymin && zmin && ca == -1) neq += e.hx;
+            if constexpr (xmin && zmin && cb == 1) neq -= e.hy;
+            if constexpr (xmin && zmin && cb == -1) neq += e.hy;
+            if constexpr (xmin && ymin && cc == 1) neq -= e.hz;
+            if constexpr (xmin && ymin && cc == -1) neq += e.hz;
+            v = relax_update<ST, L::template q<a, b, c>()>(f, om, neq, e.gK[a], kYZ<LY, LZ>.w[c][b], h);
         });
     });
+}
+
+// Collision of a whole node.
+template <int LX, int LY, int LZ, int ST>
+__device__ __forceinline__ void collide3(const KArgs &p, float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q], float rho,
+                                         float jx, float jy, float jz, float ux, float uy, float uz, uint32_t h)
+{
+    constexpr int QY = Axis<LY>::Q, NR = Axis<LZ>::Q * QY;
+    Eq3<LX, LY, LZ, 0, NR> e;
+    eq3_factors<LX, LY, LZ, 0, NR>(p, rho, jx, jy, jz, ux, uy, uz, e);
+    relax3_rows<LX, LY, LZ, ST, 0, NR>(
+        p, e,
+        [&](auto Rr, auto A) -> float & {
+            constexpr int r = Rr, a = A;
+            return v[r / QY][r % QY][a];
+        },
+        h);
 }
 
 template <int LX, int LY, int LZ, int ST>
@@ -325,9 +373,10 @@ __host__ __device__ constexpr int wall_blocks3(int nx, int nz)
     return ((2 * Axis<LY>::vmax * nx * nz + kBlock - 1) / kBlock + 7) / 8 * 8;
 }
 
-// One node (x, y, z) of a step; INTERIOR: no wall emission reaches it.
+// One node (x, y, z) of a step with the random-bit seed of that step;
+// INTERIOR: no wall emission reaches it.
 template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
-__device__ __forceinline__ void step3_node(const KArgs &p, int x, int y, int z)
+__device__ __forceinline__ void step3_node(const KArgs &p, int x, int y, int z, uint32_t seed)
 {
     using L = Lat3<LX, LY, LZ, ST>;
     const int i = (z * p.ny + y) * p.nx + x;
@@ -339,7 +388,7 @@ __device__ __forceinline__ void step3_node(const KArgs &p, int x, int y, int z)
     float rho, jx, jy, jz;
     moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
     const float inv = 1.0f / rho;
-    const uint32_t h = storage_hash<ST>(p.seed, i, y);
+    const uint32_t h = storage_hash<ST>(seed, i, y);
     collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv, mix32(h));
     store3<LX, LY, LZ, ST, BCX>(p, rd, x, z * p.ny + y, v, h);
 }
@@ -378,18 +427,188 @@ step3_kernel(KArgs p)
         const int j = tile_index(p) * kBlock + (int)threadIdx.x;
         if (j >= p.nodes) return;
         node_xyz(p, j, x, y, z);
-        step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z);
+        step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z, p.seed);
     } else {
         const int wb = wall_blocks3<LY>(p.nx, p.nz);
         const int b = blockIdx.x;
         if (b < wb) {
             if (row_set_node3<LY, ROWS_WALLS>(p, b * kBlock + (int)threadIdx.x, x, y, z))
-                step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z);
+                step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z, p.seed);
             return;
         }
         const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * kBlock + (int)threadIdx.x;
-        if (row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z)) step3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, x, y, z);
+        if (row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z)) step3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, x, y, z, p.seed);
     }
+}
+
+// ------------------------------------------- the split three-dimensional step
+// Lattices above 144 velocities (G-D3Q343: 343 populations do not fit one
+// lane's registers beside the collision) split each node over kSplit3 waves
+// of a block: wave g holds the velocity rows [split3_row(g), split3_row(g+1))
+// of its 64 nodes (row r = c QY + b, QX populations each), pulls, sums,
+// relaxes and stores only those; the partial sums of mass and momentum meet
+// in LDS and are added in wave order.  Every wave computes the equilibrium
+// factors and the wall rates of the whole node (cheap next to the
+// populations).  Batches take no such lattice (the one-lane node code would
+// live in scratch memory).
+template <int LX, int LY, int LZ, int ST>
+constexpr bool split3()
+{
+    return Lat3<LX, LY, LZ, ST>::Q > 144;
+}
+constexpr int kSplit3 = 4;                      // waves per node
+constexpr int kSplit3Nodes = kBlock / kSplit3;  // nodes per block
+template <int LY, int LZ>
+__host__ __device__ constexpr int split3_row(int g)
+{
+    return (Axis<LY>::Q * Axis<LZ>::Q * g + kSplit3 - 1) / kSplit3;
+}
+
+// Blocks of the wall rows of a split step with walls (a multiple of 8).
+template <int LY>
+__host__ __device__ constexpr int wall_blocks3_split(int nx, int nz)
+{
+    return ((2 * Axis<LY>::vmax * nx * nz + kSplit3Nodes - 1) / kSplit3Nodes + 7) / 8 * 8;
+}
+
+// Mass and momentum sums of the velocity rows [R0, R1) (working values).
+template <int LX, int LY, int LZ, int R0, int R1, class At>
+__device__ __forceinline__ void moments3_rows(At &&at, float &r, float &jx, float &jy, float &jz)
+{
+    r = jx = jy = jz = 0.0f;
+    unroll_from<R0, R1>([&](auto Rr) {
+        constexpr int rr = Rr, c = rr / Axis<LY>::Q, b = rr % Axis<LY>::Q;
+        constexpr int cb = Axis<LY>::c(b), cc = Axis<LZ>::c(c);
+        float rs = 0.0f, rx = 0.0f;
+        unroll<Axis<LX>::Q>([&](auto A) {
+            constexpr int ca = Axis<LX>::c((int)A);
+            const float f = at(Rr, A);
+            rs += f;
+            if constexpr (ca != 0) rx = __builtin_fmaf((float)ca, f, rx);
+        });
+        r += rs;
+        jx += rx;
+        if constexpr (cb != 0) jy = __builtin_fmaf((float)cb, rs, jy);
+        if constexpr (cc != 0) jz = __builtin_fmaf((float)cc, rs, jz);
+    });
+}
+
+// Wave g of a split node: its rows of node (x, y, z) pulled and summed into
+// the exchange, then (after the block's barrier, which every wave reaches
+// once) the node's moments from the exchange, its rows relaxed and, for a
+// valid node, stored.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
+__device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y, int z, bool valid,
+                                            float (&xch)[kSplit3][4][64], int lane)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    constexpr int QX = L::QX, NR = split3_row<LY, LZ>(1);  // the largest part
+    static_assert(BCX == BCX_WRAP, "the split step is built for compact rows");
+    const int i = (z * p.ny + y) * p.nx + x;
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
+    const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+    const uint32_t h = storage_hash<ST>(p.seed, i, y);
+    float v[NR][QX];
+    float rw[2];
+    wall_rates3<LX, LY, LZ, ST, BCX, BCY, INTERIOR>(p, rs, xa, y, z, rw);
+    unroll<kSplit3>([&](auto G) {
+        constexpr int R0 = split3_row<LY, LZ>(G), R1 = split3_row<LY, LZ>(G + 1);
+        if (g == G) {
+            unroll_from<R0, R1>([&](auto Rr) {
+                constexpr int r = Rr;
+                pull3_row<LX, LY, LZ, ST, BCX, BCY, INTERIOR, r % L::QY, r / L::QY>(p, rs, xa, y, z, rw, v[r - R0]);
+            });
+            float m[4];
+            moments3_rows<LX, LY, LZ, R0, R1>([&](auto Rr, auto A) -> float & { return v[(int)Rr - R0][(int)A]; },
+                                              m[0], m[1], m[2], m[3]);
+            for (int k = 0; k < 4; ++k) xch[G][k][lane] = m[k];
+        }
+    });
+    __syncthreads();
+    float m[4];
+    for (int k = 0; k < 4; ++k) m[k] = ((xch[0][k][lane] + xch[1][k][lane]) + xch[2][k][lane]) + xch[3][k][lane];
+    const float rho = L::shifted ? kShift3<LX, LY, LZ>.sum + m[0] : m[0];
+    const float inv = 1.0f / rho;
+    const uint32_t off = (uint32_t)((z * p.ny + y) * p.nxp + x) * (uint32_t)L::EB;
+    unroll<kSplit3>([&](auto G) {
+        constexpr int R0 = split3_row<LY, LZ>(G), R1 = split3_row<LY, LZ>(G + 1);
+        if (g == G) {
+            auto at = [&](auto Rr, auto A) -> float & { return v[(int)Rr - R0][(int)A]; };
+            Eq3<LX, LY, LZ, R0, R1> e;
+            eq3_factors<LX, LY, LZ, R0, R1>(p, rho, m[1], m[2], m[3], m[1] * inv, m[2] * inv, m[3] * inv, e);
+            relax3_rows<LX, LY, LZ, ST, R0, R1>(p, e, at, mix32(h));
+            if (valid) {
+                unroll_from<R0, R1>([&](auto Rr) {
+                    constexpr int r = Rr, c = r / L::QY, b = r % L::QY;
+                    unroll<QX>([&](auto A) {
+                        constexpr int a = A, q = L::template q<a, b, c>();
+                        uint32_t rb = 0;
+                        if constexpr (ST == ST_BF16SR) rb = rnd_of<q>(h);
+                        st<ST>(rd, off, (uint32_t)q * p.plane_bytes, v[r - R0][a], rb);
+                    });
+                });
+            }
+        }
+    });
+}
+
+// One step of a split lattice: 64 nodes per block, node j of the block in
+// lane j of each of its four waves.  Periodic y: every node alike.  Walls:
+// the first blocks (a multiple of 8) take the rows next to the walls, the
+// others the interior rows.  Lanes past the last node step an in-bounds node
+// of their set and store nothing (every wave must reach the barrier).
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void step3_split_kernel(KArgs p)
+{
+    constexpr int R = Axis<LY>::vmax;
+    __shared__ float xch[kSplit3][4][64];
+    const int g = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    int x = 0, y = 0, z = 0;
+    if constexpr (BCY != BCY_WALL) {
+        const int j = tile_index(p) * kSplit3Nodes + lane;
+        const bool valid = j < p.nodes;
+        if (valid) node_xyz(p, j, x, y, z);
+        split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, lane);
+    } else {
+        const int wb = wall_blocks3_split<LY>(p.nx, p.nz);
+        const int b = blockIdx.x;
+        if (b < wb) {
+            const bool valid = row_set_node3<LY, ROWS_WALLS>(p, b * kSplit3Nodes + lane, x, y, z);
+            if (!valid) x = y = z = 0;
+            split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, lane);
+        } else {
+            const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * kSplit3Nodes + lane;
+            const bool valid = row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z);
+            if (!valid) {
+                x = z = 0;
+                y = R;
+            }
+            split3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, g, x, y, z, valid, xch, lane);
+        }
+    }
+}
+
+// Batched step of three-dimensional members (see batch_step_kernel): block
+// b takes tile b of the table, nodes first .. first + count - 1 of its
+// member in the order (z, y, x), each by the single-lattice node code with
+// the pull that checks for wall emission (which loads the same values for an
+// interior node): a batched lattice is bitwise the lattice stepped alone.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Lat3<LX, LY, LZ, ST>::Q <= 125 ? 2 : 1))) void
+batch_step3_kernel(const BatchTile *__restrict__ tiles, const KArgs *__restrict__ args,
+                   const int32_t *__restrict__ phase, const int64_t *__restrict__ t0,
+                   const int64_t *__restrict__ bstep, int32_t launch)
+{
+    const BatchTile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const int64_t s = *bstep + launch;
+    const KArgs &p = args[2 * t.member + (phase[t.member] ^ (int)(s & 1))];
+    const int j = t.first + (int)threadIdx.x;
+    if (j >= p.nodes) return;
+    int x, y, z;
+    node_xyz(p, j, x, y, z);
+    step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z, draws_bits<ST>() ? step_seed(t0[t.member] + s + 1) : 0u);
 }
 
 // Moments of f(t) (FP64 sums of the stored values), as observe_kernel.

@@ -5,7 +5,7 @@
 // -DGLBM_EVEN=1 builds the lattices of G-D1Q(2N+2) axes instead of
 // G-D1Q(2N+1) ones.  -DGLBM_COMPACT=0 builds the one-dimensional lattices
 // (padded rows), -DGLBM_COMPACT=1 the two-dimensional ones (periodic x in
-// compact rows).  Each (axis kind, dimension, level) is its own object file
+// compact rows), with -DGLBM_WALLS=1 those with walls across y.  Each (axis kind, dimension, level) is its own object file
 // so the build runs in parallel.
 #include "glbm_internal.h"
 
@@ -16,7 +16,12 @@ template <int LX, int LY, int ST, int BCX, int BCY>
 struct Launchers {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
-        if constexpr (BCY == BCY_WALL && BCX == BCX_WRAP && split_node<LX, LY, ST>()) {
+        if constexpr (BCY == BCY_PERIODIC && BCX == BCX_WRAP && split_node<LX, LY, ST>()) {
+            // more than 144 velocities: each node split over a wave pair
+            const int nodes = a.nx * a.ny;
+            hipLaunchKernelGGL((step_kernel_split<LX, LY, ST, BCX, BCY>),
+                               dim3((nodes + kSplitNodes - 1) / kSplitNodes), dim3(kBlock), 0, s, a);
+        } else if constexpr (BCY == BCY_WALL && BCX == BCX_WRAP && split_node<LX, LY, ST>()) {
             // more than 144 velocities: the interior rows with each node split
             // over a wave pair, then the rows next to the walls
             constexpr int R = Axis<LY>::vmax;
@@ -144,6 +149,21 @@ void add_all_storages()
 #define GLBM_REG3(E, C, L) register_##E##_##C##_##L
 #define GLBM_REG(E, C, L) GLBM_REG3(E, C, L)
 
+// The registration function's kind: 0 one-dimensional, 1 two-dimensional
+// (periodic y for the symmetric lattices; the mixed lattices), 2 the
+// symmetric lattices with walls (-DGLBM_WALLS=1: their own object, so that
+// the largest levels build in parallel halves).
+#ifndef GLBM_WALLS
+#define GLBM_WALLS 0
+#endif
+#if !GLBM_COMPACT
+#define GLBM_KIND 0
+#elif GLBM_WALLS && GLBM_LEVEL >= 1 && GLBM_LEVEL <= 7
+#define GLBM_KIND 2
+#else
+#define GLBM_KIND 1
+#endif
+
 // Axis codes of this object: the G-D1Q(2N+1) axis of level N, or the
 // G-D1Q(2N+2) one (code kEven + N).
 #if GLBM_EVEN
@@ -158,22 +178,25 @@ void add_all_storages()
 #if !GLBM_EVEN || !GLBM_COMPACT
 #error "levels above 7 exist only for the even axis of the mixed lattices (-DGLBM_EVEN=1 -DGLBM_COMPACT=1)"
 #endif
-void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, GLBM_LEVEL)()
+void GLBM_REG(GLBM_EVEN, GLBM_KIND, GLBM_LEVEL)()
 {
     add_all_storages<1, GLBM_AX(GLBM_LEVEL), BCX_WRAP, BCY_WALL>();
 }
 #elif GLBM_LEVEL >= 1
-void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, GLBM_LEVEL)()
+void GLBM_REG(GLBM_EVEN, GLBM_KIND, GLBM_LEVEL)()
 {
     constexpr int N = GLBM_LEVEL, A = GLBM_AX(GLBM_LEVEL);
 #if GLBM_COMPACT
     // two dimensions, the same axis twice, periodic x in compact rows:
-    // periodic or walls across y (the symmetric even lattices up to N = 6:
-    // (2N+2)^2 <= 196 velocities)
-    if constexpr (!GLBM_EVEN || N <= 6) {
-        add_all_storages<A, A, BCX_WRAP, BCY_PERIODIC>();
-        add_all_storages<A, A, BCX_WRAP, BCY_WALL>();
-    }
+    // periodic y, or walls across y (-DGLBM_WALLS=1).  Above 144 velocities
+    // (N = 7 odd and even) the steps of interior nodes run split over wave
+    // pairs; their other one-node launches (wall rows, batched steps,
+    // observation) take one wave and may spill to scratch.
+#if GLBM_WALLS
+    add_all_storages<A, A, BCX_WRAP, BCY_WALL>();
+#else
+    add_all_storages<A, A, BCX_WRAP, BCY_PERIODIC>();
+#endif
 #else
     // one dimension: periodic or fixed equilibrium ends (padded rows)
     add_all_storages<A, 0, BCX_PERIODIC, BCY_PERIODIC>();
@@ -185,7 +208,7 @@ void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, GLBM_LEVEL)()
 // Mixed lattices D1Q3 (streamwise x) x G-D1Q(2N+1) or G-D1Q(2N+2) (across the
 // walls), the form the channel flows of sections 5.3-5.4 use; periodic x in
 // compact rows.
-void GLBM_REG(GLBM_EVEN, GLBM_COMPACT, 0)()
+void GLBM_REG(GLBM_EVEN, GLBM_KIND, 0)()
 {
     constexpr int BX = BCX_WRAP;
 #if !GLBM_EVEN

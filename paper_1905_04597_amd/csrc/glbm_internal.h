@@ -35,18 +35,25 @@ struct Variant {
 // (with the row layout), bc_y; three-dimensional lattices in their own.
 Variant *variant_slot(int ax, int ay, int storage, int bcx, int bcy);
 Variant *variant3_slot(int ax, int ay, int az, int storage, int bcx, int bcy);
-void register3();
+// three dimensions: one per object of glbm_inst3.hip
+#define GLBM_OBJECTS3(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#define GLBM_DECLARE_REGISTER3(K) void register3_##K();
+GLBM_OBJECTS3(GLBM_DECLARE_REGISTER3)
 
 // One registration function per object file of glbm_inst.hip,
-// register_E_C_L(): E = 1 for the lattices with G-D1Q(2N+2) axes, C = 0 for
+// register_E_K_L(): E = 1 for the lattices with G-D1Q(2N+2) axes; K = 0 for
 // the one-dimensional lattices (padded rows), 1 for the two-dimensional ones
-// (compact rows), L = level (0: the mixed lattices with a D1Q3 x axis up to
-// level 7; 8..13: the mixed lattice with the even axis of that level).
+// (compact rows) with periodic y and for the mixed lattices, 2 for the
+// symmetric two-dimensional ones with walls; L = level (0: the mixed
+// lattices with a D1Q3 x axis up to level 7; 8..13: the mixed lattice with
+// the even axis of that level).
 #define GLBM_OBJECTS(X)                                                                                        \
-    X(0, 0, 1) X(0, 0, 2) X(0, 0, 3) X(0, 0, 4) X(0, 0, 5) X(0, 0, 6) X(0, 0, 7)                   \
+    X(0, 0, 1) X(0, 0, 2) X(0, 0, 3) X(0, 0, 4) X(0, 0, 5) X(0, 0, 6) X(0, 0, 7)                               \
     X(0, 1, 0) X(0, 1, 1) X(0, 1, 2) X(0, 1, 3) X(0, 1, 4) X(0, 1, 5) X(0, 1, 6) X(0, 1, 7)                   \
-    X(1, 0, 1) X(1, 0, 2) X(1, 0, 3) X(1, 0, 4) X(1, 0, 5) X(1, 0, 6) X(1, 0, 7)                   \
+    X(0, 2, 1) X(0, 2, 2) X(0, 2, 3) X(0, 2, 4) X(0, 2, 5) X(0, 2, 6) X(0, 2, 7)                               \
+    X(1, 0, 1) X(1, 0, 2) X(1, 0, 3) X(1, 0, 4) X(1, 0, 5) X(1, 0, 6) X(1, 0, 7)                               \
     X(1, 1, 0) X(1, 1, 1) X(1, 1, 2) X(1, 1, 3) X(1, 1, 4) X(1, 1, 5) X(1, 1, 6) X(1, 1, 7)                   \
+    X(1, 2, 1) X(1, 2, 2) X(1, 2, 3) X(1, 2, 4) X(1, 2, 5) X(1, 2, 6) X(1, 2, 7)                               \
     X(1, 1, 8) X(1, 1, 9) X(1, 1, 10) X(1, 1, 11) X(1, 1, 12) X(1, 1, 13)
 #define GLBM_DECLARE_REGISTER(E, C, L) void register_##E##_##C##_##L();
 GLBM_OBJECTS(GLBM_DECLARE_REGISTER)

@@ -140,8 +140,11 @@ def three_d_summary(trace: str, command: str, steps: int = 20, storage: str = "f
     import re
 
     eb = 4 if storage.startswith("f32") else 2
-    shapes = {(1, 1, 1): (27, 256 * 256 * 128), (2, 2, 2): (125, 128 ** 3), (1, 3, 1): (63, 256 * 128 * 128),
-              (1, 11, 1): (72, 256 * 128 * 128)}
+    # axis codes: N for G-D1Q(2N+1), 16 + N for G-D1Q(2N+2)
+    shapes = {(1, 1, 1): (27, 256 * 256 * 128), (2, 2, 2): (125, 128 ** 3), (3, 3, 3): (343, 128 ** 3)}
+    for n in range(2, 8):
+        shapes[(1, n, 1)] = (9 * (2 * n + 1), 256 * 128 * 128)
+        shapes[(1, 16 + n, 1)] = (9 * (2 * n + 2), 256 * 128 * 128)
     stats = kernel_stats(trace)
     path = os.path.join(PROFILES, "step3_kernel_3d_sweep_%s.md" % storage)
     with open(path, "w") as fh:
@@ -155,7 +158,7 @@ def three_d_summary(trace: str, command: str, steps: int = 20, storage: str = "f
         fh.write("\n## Step kernels\n\n| lattice (axis codes x, y, z) | Q | nodes | avg us | algorithmic GB/s |"
                  "\n|---|---|---|---|---|\n")
         for st in stats:
-            m = re.search(r"step3_kernel<(\d+), (\d+), (\d+),", st["name"])
+            m = re.search(r"step3_(?:split_)?kernel<(\d+), (\d+), (\d+),", st["name"])
             if not m:
                 continue
             key = tuple(int(g) for g in m.groups())

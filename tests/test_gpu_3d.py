@@ -123,25 +123,83 @@ def test_3d_free_streaming_permutation_bitwise():
     assert np.array_equal(gpu.populations().cpu().numpy(), f0)
 
 
-def test_3d_members_are_refused_by_batches():
-    cfg = glbm.make_config(3, 1, 1, 8, 4, tau=0.8, level_z=1, nz=4)
+BATCH3 = [
+    # (levels, even_y, (nx, ny, nz), storage, bc_y)
+    ((1, 1, 1), False, (9, 5, 4), "f32_shifted", "periodic"),
+    ((2, 2, 2), False, (13, 6, 3), "bf16_shifted_sr", "wall"),
+    ((1, 3, 1), True, (21, 16, 2), "f32_shifted", "wall"),
+    ((1, 7, 1), False, (5, 17, 3), "f32", "wall"),
+    ((1, 7, 1), True, (7, 31, 2), "bf16_shifted_sr", "wall"),
+    ((1, 4, 1), False, (300, 9, 2), "bf16_shifted", "periodic"),
+]
+
+
+@pytest.mark.parametrize("opts", [dict(tile_nodes=64, graph_steps=3), dict(tile_nodes=256, streams=4,
+                                                                            resident_nodes=4096)],
+                         ids=["tiles64_graph3", "tiles256_streams4_resident"])
+def test_3d_members_in_batches_bitwise(opts):
+    """Three-dimensional members (several lattices, storages and boundaries,
+    beside a two-dimensional one) stepped in a batch: bitwise the populations
+    of each member stepped alone (stochastic-rounding seeds included); a
+    resident option leaves the 3D members tiled."""
+    import torch
+
+    rng = np.random.default_rng(31)
+    cfgs = []
+    for (lx, ly, lz), ev, (nx, ny, nz), st, bcy in BATCH3:
+        th_y = (4 * ly + 3) / 3.0 if ev else ly / 3.0
+        U = 0.04 * math.sqrt(th_y)
+        g = 0.0 if st == "bf16_shifted" else 1e-4
+        wall = (-U, U) if bcy == "wall" else (0.0, 0.0)
+        cfgs.append(glbm.make_config(3, lx, ly, nx, ny, tau=float(rng.uniform(0.6, 1.2)), bc_y=bcy, wall_u=wall,
+                                     g=g, storage=st, even_y=ev, level_z=lz, nz=nz))
+    cfgs.append(glbm.make_config(2, 2, 2, 40, 12, tau=0.9, bc_y="wall", wall_u=(0.02, -0.02), g=1e-4,
+                                 storage="f32_shifted"))
+    print("\n[3d] batch of %d members, options %s" % (len(cfgs), opts), flush=True)
+    alone, batched = [], []
+    for c in cfgs:
+        pair = [glbm.Solver(c), glbm.Solver(c)]
+        shape = pair[0].shape
+        fields = [(1.0 + 0.05 * rng.uniform(-1, 1, shape)).astype(np.float32)]
+        fields += [(0.05 * rng.uniform(-1, 1, shape)).astype(np.float32) for _ in range(len(shape))]
+        for s in pair:
+            s.init_fields(*fields)
+        alone.append(pair[0])
+        batched.append(pair[1])
+    steps = 7
+    for s in alone:
+        s.step(steps)
+    with glbm.Batch(batched, **opts) as b:
+        b.step(steps)
+    torch.cuda.synchronize()
+    for i, (a, bb) in enumerate(zip(alone, batched)):
+        pa, pb = a.populations(), bb.populations()
+        torch.cuda.synchronize()
+        assert torch.equal(pa, pb), "member %d" % i
+    for s in alone + batched:
+        s.close()
+
+
+def test_split_lattice_is_refused_by_batches():
+    cfg = glbm.make_config(3, 3, 3, 8, 8, tau=0.8, level_z=3, nz=4)
     s = glbm.Solver(cfg)
     s.init_fields()
-    with pytest.raises(glbm.GlbmError, match="one- and two-dimensional"):
+    with pytest.raises(glbm.GlbmError, match="no batched step"):
         glbm.Batch([s])
+    s.close()
 
 
 BENCH_SHAPES = [
     # the three-dimensional lattices and shapes of the bench sweep
     ((1, 1, 1), False, (256, 256, 128)),
     ((2, 2, 2), False, (128, 128, 128)),
-    ((1, 3, 1), False, (256, 128, 128)),
-    ((1, 3, 1), True, (256, 128, 128)),
-]
+    ((3, 3, 3), False, (128, 128, 128)),
+] + [((1, n, 1), ev, (256, 128, 128)) for ev in (False, True) for n in range(2, 8)]
+BENCH_IDS = ["d3q27", "g_d3q125", "g_d3q343"] + ["d1q3xd1q%dxd1q3" % (2 * n + (2 if ev else 1))
+                                     for ev in (False, True) for n in range(2, 8)]
 
 
-@pytest.mark.parametrize("levels,even_y,shape", BENCH_SHAPES, ids=["d3q27", "g_d3q125", "d1q3xd1q7xd1q3",
-                                                                   "d1q3xd1q8xd1q3"])
+@pytest.mark.parametrize("levels,even_y,shape", BENCH_SHAPES, ids=BENCH_IDS)
 def test_3d_bench_shapes_against_oracle_columns(levels, even_y, shape):
     """The bench's three-dimensional runs at full size (walls across y,
     g = 1e-5, Kn = 0.1, from rest, FP32 deviation storage; here with moving
