@@ -155,9 +155,11 @@ typedef struct glbm_solver glbm_t;
 size_t glbm_population_bytes(const glbm_config *cfg);
 
 /* Device bytes a solver of cfg occupies in total: its two population buffers
- * (caller-owned) plus the FP64 statistics buffers the library allocates on
- * the first glbm_stats call (a fixed number of partial-sum rows, at most
- * 2048 x 13 doubles); 0 if cfg is invalid.  For HBM-budget admission. */
+ * (caller-owned), the FP64 statistics buffers the library allocates on the
+ * first glbm_stats call (a fixed number of partial-sum rows, at most
+ * 2048 x 13 doubles) and, for a three-dimensional lattice with walls, the
+ * per-column wall factors the library allocates at glbm_create (2 nx nz
+ * floats); 0 if cfg is invalid.  For HBM-budget admission. */
 size_t glbm_required_bytes(const glbm_config *cfg);
 
 /* Create a solver over caller-owned device buffers pop_a and pop_b, each of
@@ -167,7 +169,9 @@ size_t glbm_required_bytes(const glbm_config *cfg);
  * nu = theta tau, section 5.2: tau = Kn H / sqrt(2 theta)); the collision
  * frequency of Eq. maineq01 is 1 / (tau + 1/2).  The state is undefined until
  * glbm_init_fields or glbm_init_populations.  *out receives the handle; the
- * caller keeps the buffers alive until glbm_destroy.
+ * caller keeps the buffers alive until glbm_destroy.  A three-dimensional
+ * lattice with walls allocates its wall factors here (see
+ * glbm_required_bytes); nothing else is allocated before glbm_stats.
  * Errors: GLBM_ERR_INVALID for a bad configuration (including omega outside
  * (0, 2), ny < 2 Ny with walls, walls combined with equilibrium ends, a
  * buffer above 4 GiB), GLBM_ERR_UNSUPPORTED for level combinations not built

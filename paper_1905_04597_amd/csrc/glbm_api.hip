@@ -234,6 +234,7 @@ struct glbm_solver {
     KArgs base;
     int grid;
     double *d_partials, *d_out, *h_out;
+    float *d_wrate;  // three-dimensional walls: per-column wall factors of a step
     int device;
     bool in_batch;
 };
@@ -262,11 +263,18 @@ static size_t stats_bytes(int64_t nodes)
     return sizeof(double) * kNumStats * ((size_t)stat_blocks(nodes) + 1);
 }
 
+// Bytes of the wall factors of a three-dimensional lattice with walls (the
+// bottom and top factor of every (x, z) column), 0 otherwise.
+static size_t wrate_bytes(const glbm_config *cfg, const Geometry &g)
+{
+    return cfg->dims == 3 && cfg->bc_y == GLBM_BC_WALL ? 2 * sizeof(float) * (size_t)(g.nx * g.nz) : 0;
+}
+
 size_t glbm_required_bytes(const glbm_config *cfg)
 {
     Geometry g;
     if (check_config(cfg, &g) != GLBM_OK) return 0;
-    return 2 * (size_t)g.buf_bytes + stats_bytes(g.nx * g.ny * g.nz);
+    return 2 * (size_t)g.buf_bytes + stats_bytes(g.nx * g.ny * g.nz) + wrate_bytes(cfg, g);
 }
 
 int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, glbm_t **out)
@@ -344,6 +352,14 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
         a.uw[side] = (float)U;
     }
 
+    if (const size_t wb = wrate_bytes(cfg, g)) {
+        hipError_t e = hipMalloc((void **)&h->d_wrate, wb);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "allocating the wall factors");
+        }
+        a.wrate = h->d_wrate;
+    }
     // the FP64 statistics buffers are allocated by the first glbm_stats call,
     // so that a solver that never asks for them costs no device allocation
     *out = h;
@@ -527,13 +543,14 @@ int glbm_destroy(glbm_t *h)
 {
     if (!h) return GLBM_OK;
     if (h->in_batch) return fail(GLBM_ERR_STATE, "the solver belongs to a batch: destroy the batch first");
+    // kernels may still use these buffers
+    if (h->d_partials || h->d_wrate) (void)hipStreamSynchronize(h->stream);
     if (h->d_partials) {
-        // statistics kernels may still use these buffers
-        (void)hipStreamSynchronize(h->stream);
         (void)hipFree(h->d_partials);
         (void)hipFree(h->d_out);
         (void)hipHostFree(h->h_out);
     }
+    if (h->d_wrate) (void)hipFree(h->d_wrate);
     delete h;
     return GLBM_OK;
 }

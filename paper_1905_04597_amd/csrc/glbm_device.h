@@ -334,6 +334,9 @@ struct KArgs {
     const float *i_rho, *i_ux, *i_uy, *i_f;
     const float *i_uz;    // three dimensions
     void *dst2;           // init: buffer receiving f(0)
+    // three-dimensional walls: the wall factors of this step per (x, z)
+    // column, bottom [nz][nx] then top, from the wall pre-pass
+    float *wrate;
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a

@@ -131,20 +131,36 @@ __device__ __forceinline__ float wall_absorbed3(const KArgs &p, rsrc_t rs, const
     return s;
 }
 
-// Wall re-emission factors of a node in row y: rho_w / (J+ sum_a fw_a) for
-// the bottom and top walls (zero out of their reach; INTERIOR: none).
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
-__device__ __forceinline__ void wall_rates3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
-                                            int z, float (&rw)[2])
+// Wall re-emission factor of the column at (x, z): rho_w / (J+ sum_a fw_a),
+// rho_w the mass the wall absorbs there in this streaming.
+template <int LX, int LY, int LZ, int ST, int BCX, bool BOTTOM>
+__device__ __forceinline__ float wall_factor3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int z)
+{
+    constexpr double jp = kYZ<LY, LZ>.jplus;
+    return wall_absorbed3<LX, LY, LZ, ST, BCX, BOTTOM>(p, rs, xa, z, nullptr) / (float)(jp * p.fwsum[BOTTOM ? 0 : 1]);
+}
+
+// Wall factors of a node in row y for the bottom and top walls (zero out of
+// their reach; INTERIOR: none).  PRE: read from the wall pre-pass of this
+// step (wall_rate3_kernel, the same arithmetic once per column) instead of
+// summed by the lane: every one of the 2 R wall rows of a column would
+// otherwise repeat the column's sum (R (R + 1) / 2 rows of QX QZ loads).
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR, bool PRE = false>
+__device__ __forceinline__ void wall_rates3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int x,
+                                            int y, int z, float (&rw)[2])
 {
     rw[0] = 0.0f;
     rw[1] = 0.0f;
     if constexpr (BCY == BCY_WALL && !INTERIOR) {
-        constexpr double jp = kYZ<LY, LZ>.jplus;
         constexpr int reach = Axis<LY>::vmax;
-        if (y < reach) rw[0] = wall_absorbed3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z, nullptr) / (float)(jp * p.fwsum[0]);
-        if (y >= p.ny - reach)
-            rw[1] = wall_absorbed3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z, nullptr) / (float)(jp * p.fwsum[1]);
+        if constexpr (PRE) {
+            const int col = z * p.nx + x;
+            if (y < reach) rw[0] = p.wrate[col];
+            if (y >= p.ny - reach) rw[1] = p.wrate[p.nx * p.nz + col];
+        } else {
+            if (y < reach) rw[0] = wall_factor3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z);
+            if (y >= p.ny - reach) rw[1] = wall_factor3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z);
+        }
     }
 }
 
@@ -189,12 +205,12 @@ __device__ __forceinline__ void pull3_row(const KArgs &p, rsrc_t rs, const XAddr
 }
 
 // Pre-collision populations of node (x, y, z): pulled, or emitted by a wall.
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR = false>
-__device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y, int z,
-                                      float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q])
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR = false, bool PRE = false>
+__device__ __forceinline__ void pull3(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int x, int y,
+                                      int z, float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q])
 {
     float rw[2];
-    wall_rates3<LX, LY, LZ, ST, BCX, BCY, INTERIOR>(p, rs, xa, y, z, rw);
+    wall_rates3<LX, LY, LZ, ST, BCX, BCY, INTERIOR, PRE>(p, rs, xa, x, y, z, rw);
     unroll<Axis<LZ>::Q>([&](auto C) {
         unroll<Axis<LY>::Q>([&](auto B) {
             pull3_row<LX, LY, LZ, ST, BCX, BCY, INTERIOR, (int)B, (int)C>(p, rs, xa, y, z, rw, v[C][B]);
@@ -366,109 +382,40 @@ __device__ __forceinline__ void node_xyz(const KArgs &p, int i, int &x, int &y, 
     y = r - z * p.ny;
 }
 
-// Blocks of the wall rows of a 3D step with walls (a multiple of 8).
+// Blocks of the wall rows of a 3D step with walls, nb nodes per block (a
+// multiple of 8).
 template <int LY>
-__host__ __device__ constexpr int wall_blocks3(int nx, int nz)
+__host__ __device__ constexpr int wall_blocks3(int nx, int nz, int nb)
 {
-    return ((2 * Axis<LY>::vmax * nx * nz + kBlock - 1) / kBlock + 7) / 8 * 8;
+    return ((2 * Axis<LY>::vmax * nx * nz + nb - 1) / nb + 7) / 8 * 8;
 }
 
-// One node (x, y, z) of a step with the random-bit seed of that step;
-// INTERIOR: no wall emission reaches it.
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
-__device__ __forceinline__ void step3_node(const KArgs &p, int x, int y, int z, uint32_t seed)
+// ------------------------------------------- nodes split over waves
+// Above 125 velocities a node's populations and the collision do not fit one
+// lane's registers at two waves per SIMD (at 126-144 the compiler spilled to
+// accumulation registers and ran one wave; the 343 of G-D3Q343 do not fit at
+// all), so the step splits each node over split3_waves waves of a block:
+// wave g holds the velocity rows [split3_row(g), split3_row(g + 1)) of its
+// nodes (row r = c QY + b, QX populations each), pulls, sums, relaxes and
+// stores only those; the partial sums of mass and momentum meet in LDS and
+// are added in wave order.  Each wave forms the equilibrium factors of the
+// whole node (cheap next to the populations).  The one-lane node code (the
+// batched step) adds the same partial sums in the same order, so a node
+// gives the same bits split or not.
+template <int LX, int LY, int LZ, int ST>
+constexpr int split3_waves()
 {
-    using L = Lat3<LX, LY, LZ, ST>;
-    const int i = (z * p.ny + y) * p.nx + x;
-    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
-    const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
-    const XAddr<LX, L::EB, BCX> xa(x, p.nx);
-    float v[L::QZ][L::QY][L::QX];
-    pull3<LX, LY, LZ, ST, BCX, BCY, INTERIOR>(p, rs, xa, y, z, v);
-    float rho, jx, jy, jz;
-    moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
-    const float inv = 1.0f / rho;
-    const uint32_t h = storage_hash<ST>(seed, i, y);
-    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv, mix32(h));
-    store3<LX, LY, LZ, ST, BCX>(p, rd, x, z * p.ny + y, v, h);
+    return Lat3<LX, LY, LZ, ST>::Q > 144 ? 4 : Lat3<LX, LY, LZ, ST>::Q > 125 ? 2 : 1;
 }
-
-// Node of launch index j within a set of rows of every z plane: the rows
-// that take no wall emission, or the rows next to the walls (as many as the
-// fastest y velocity reaches); false outside the set.
-template <int LY, int ROWS>
-__device__ __forceinline__ bool row_set_node3(const KArgs &p, int j, int &x, int &y, int &z)
-{
-    constexpr int R = Axis<LY>::vmax;
-    const int rows = ROWS == ROWS_INTERIOR ? p.ny - 2 * R : 2 * R;
-    const int per = rows * p.nx;
-    if (j >= per * p.nz) return false;
-    z = j / per;
-    const int r = j - z * per;
-    const int yr = r / p.nx;
-    x = r - yr * p.nx;
-    y = ROWS == ROWS_INTERIOR ? yr + R : (yr < R ? yr : p.ny - 2 * R + yr);
-    return true;
-}
-
-// One step.  Periodic y: every node alike.  Walls: one launch whose first
-// blocks (a multiple of 8, so that the others keep their XCD order) step the
-// rows next to the walls and the others the interior rows, whose pull has no
-// branches (all of a node's loads in flight together).
-// Two waves per SIMD asked of the register allocator up to 125 velocities
-// (G-D3Q125 fits 256 registers without spills; left alone, the dithered FP32
-// update took it to one wave).
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Lat3<LX, LY, LZ, ST>::Q <= 125 ? 2 : 1))) void
-step3_kernel(KArgs p)
-{
-    int x, y, z;
-    if constexpr (BCY != BCY_WALL) {
-        const int j = tile_index(p) * kBlock + (int)threadIdx.x;
-        if (j >= p.nodes) return;
-        node_xyz(p, j, x, y, z);
-        step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z, p.seed);
-    } else {
-        const int wb = wall_blocks3<LY>(p.nx, p.nz);
-        const int b = blockIdx.x;
-        if (b < wb) {
-            if (row_set_node3<LY, ROWS_WALLS>(p, b * kBlock + (int)threadIdx.x, x, y, z))
-                step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z, p.seed);
-            return;
-        }
-        const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * kBlock + (int)threadIdx.x;
-        if (row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z)) step3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, x, y, z, p.seed);
-    }
-}
-
-// ------------------------------------------- the split three-dimensional step
-// Lattices above 144 velocities (G-D3Q343: 343 populations do not fit one
-// lane's registers beside the collision) split each node over kSplit3 waves
-// of a block: wave g holds the velocity rows [split3_row(g), split3_row(g+1))
-// of its 64 nodes (row r = c QY + b, QX populations each), pulls, sums,
-// relaxes and stores only those; the partial sums of mass and momentum meet
-// in LDS and are added in wave order.  Every wave computes the equilibrium
-// factors and the wall rates of the whole node (cheap next to the
-// populations).  Batches take no such lattice (the one-lane node code would
-// live in scratch memory).
 template <int LX, int LY, int LZ, int ST>
 constexpr bool split3()
 {
-    return Lat3<LX, LY, LZ, ST>::Q > 144;
+    return split3_waves<LX, LY, LZ, ST>() > 1;
 }
-constexpr int kSplit3 = 4;                      // waves per node
-constexpr int kSplit3Nodes = kBlock / kSplit3;  // nodes per block
-template <int LY, int LZ>
+template <int LY, int LZ, int K>
 __host__ __device__ constexpr int split3_row(int g)
 {
-    return (Axis<LY>::Q * Axis<LZ>::Q * g + kSplit3 - 1) / kSplit3;
-}
-
-// Blocks of the wall rows of a split step with walls (a multiple of 8).
-template <int LY>
-__host__ __device__ constexpr int wall_blocks3_split(int nx, int nz)
-{
-    return ((2 * Axis<LY>::vmax * nx * nz + kSplit3Nodes - 1) / kSplit3Nodes + 7) / 8 * 8;
+    return (Axis<LY>::Q * Axis<LZ>::Q * g + K - 1) / K;
 }
 
 // Mass and momentum sums of the velocity rows [R0, R1) (working values).
@@ -493,16 +440,128 @@ __device__ __forceinline__ void moments3_rows(At &&at, float &r, float &jx, floa
     });
 }
 
-// Wave g of a split node: its rows of node (x, y, z) pulled and summed into
-// the exchange, then (after the block's barrier, which every wave reaches
-// once) the node's moments from the exchange, its rows relaxed and, for a
-// valid node, stored.
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
-__device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y, int z, bool valid,
-                                            float (&xch)[kSplit3][4][64], int lane)
+// Mass and momentum of a whole node in registers: for a split lattice the
+// partial sums of its wave parts, added in wave order (as the split step).
+template <int LX, int LY, int LZ, int ST>
+__device__ __forceinline__ void node_moments3(const float (&v)[Axis<LZ>::Q][Axis<LY>::Q][Axis<LX>::Q], float &rho,
+                                              float &jx, float &jy, float &jz)
 {
     using L = Lat3<LX, LY, LZ, ST>;
-    constexpr int QX = L::QX, NR = split3_row<LY, LZ>(1);  // the largest part
+    constexpr int K = split3_waves<LX, LY, LZ, ST>();
+    if constexpr (K == 1) {
+        moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
+    } else {
+        float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        unroll<K>([&](auto G) {
+            constexpr int R0 = split3_row<LY, LZ, K>(G), R1 = split3_row<LY, LZ, K>(G + 1);
+            float q[4];
+            moments3_rows<LX, LY, LZ, R0, R1>(
+                [&](auto Rr, auto A) -> float { return v[(int)Rr / L::QY][(int)Rr % L::QY][(int)A]; }, q[0], q[1], q[2],
+                q[3]);
+            for (int k = 0; k < 4; ++k) m[k] = G == 0 ? q[k] : m[k] + q[k];
+        });
+        rho = L::shifted ? kShift3<LX, LY, LZ>.sum + m[0] : m[0];
+        jx = m[1];
+        jy = m[2];
+        jz = m[3];
+    }
+}
+
+// One node (x, y, z) of a step with the random-bit seed of that step;
+// INTERIOR: no wall emission reaches it; PRE: wall factors from the wall
+// pre-pass.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR, bool PRE = false>
+__device__ __forceinline__ void step3_node(const KArgs &p, int x, int y, int z, uint32_t seed)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    const int i = (z * p.ny + y) * p.nx + x;
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const rsrc_t rd = make_rsrc(p.dst, p.buf_bytes);
+    const XAddr<LX, L::EB, BCX> xa(x, p.nx);
+    float v[L::QZ][L::QY][L::QX];
+    pull3<LX, LY, LZ, ST, BCX, BCY, INTERIOR, PRE>(p, rs, xa, x, y, z, v);
+    float rho, jx, jy, jz;
+    node_moments3<LX, LY, LZ, ST>(v, rho, jx, jy, jz);
+    const float inv = 1.0f / rho;
+    const uint32_t h = storage_hash<ST>(seed, i, y);
+    collide3<LX, LY, LZ, ST>(p, v, rho, jx, jy, jz, jx * inv, jy * inv, jz * inv, mix32(h));
+    store3<LX, LY, LZ, ST, BCX>(p, rd, x, z * p.ny + y, v, h);
+}
+
+// Node of launch index j within a set of rows of every z plane: the rows
+// that take no wall emission, or the rows next to the walls (as many as the
+// fastest y velocity reaches); false outside the set.
+template <int LY, int ROWS>
+__device__ __forceinline__ bool row_set_node3(const KArgs &p, int j, int &x, int &y, int &z)
+{
+    constexpr int R = Axis<LY>::vmax;
+    const int rows = ROWS == ROWS_INTERIOR ? p.ny - 2 * R : 2 * R;
+    const int per = rows * p.nx;
+    if (j >= per * p.nz) return false;
+    z = j / per;
+    const int r = j - z * per;
+    const int yr = r / p.nx;
+    x = r - yr * p.nx;
+    y = ROWS == ROWS_INTERIOR ? yr + R : (yr < R ? yr : p.ny - 2 * R + yr);
+    return true;
+}
+
+// Wall pre-pass of a step with walls: the bottom and top wall factors of
+// every (x, z) column into p.wrate, one lane per column (the wall rows of
+// the step then read them instead of each summing its column).
+template <int LX, int LY, int LZ, int ST, int BCX>
+__global__ __launch_bounds__(kBlock) void wall_rate3_kernel(KArgs p)
+{
+    const int col = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (col >= p.nx * p.nz) return;
+    const int z = col / p.nx, x = col - z * p.nx;
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const XAddr<LX, Elem<ST>::bytes, BCX> xa(x, p.nx);
+    p.wrate[col] = wall_factor3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z);
+    p.wrate[p.nx * p.nz + col] = wall_factor3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z);
+}
+
+// One step.  Periodic y: every node alike.  Walls: one launch whose first
+// blocks (a multiple of 8, so that the others keep their XCD order) step the
+// rows next to the walls (wall factors from the pre-pass) and the others the
+// interior rows, whose pull has no branches (all of a node's loads in flight
+// together).  Two waves per SIMD asked of the register allocator (up to 125
+// velocities: G-D3Q125 fits 256 registers without spills; left alone, the
+// dithered FP32 update took it to one wave).
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void step3_kernel(KArgs p)
+{
+    static_assert(!split3<LX, LY, LZ, ST>(), "split lattices step in step3_split_kernel");
+    int x, y, z;
+    if constexpr (BCY != BCY_WALL) {
+        const int j = tile_index(p) * kBlock + (int)threadIdx.x;
+        if (j >= p.nodes) return;
+        node_xyz(p, j, x, y, z);
+        step3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, x, y, z, p.seed);
+    } else {
+        const int wb = wall_blocks3<LY>(p.nx, p.nz, kBlock);
+        const int b = blockIdx.x;
+        if (b < wb) {
+            if (row_set_node3<LY, ROWS_WALLS>(p, b * kBlock + (int)threadIdx.x, x, y, z))
+                step3_node<LX, LY, LZ, ST, BCX, BCY, false, true>(p, x, y, z, p.seed);
+            return;
+        }
+        const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * kBlock + (int)threadIdx.x;
+        if (row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z)) step3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, x, y, z, p.seed);
+    }
+}
+
+// Wave g of a split node: its rows of node (x, y, z) pulled and summed into
+// the exchange slot of its wave, then (after the block's barrier, which
+// every wave reaches once) the node's moments from the K slots of its wave
+// group, its rows relaxed and, for a valid node, stored.
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
+__device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y, int z, bool valid,
+                                            float (&xch)[kBlock / 64][4][64], int wave, int lane)
+{
+    using L = Lat3<LX, LY, LZ, ST>;
+    constexpr int K = split3_waves<LX, LY, LZ, ST>();
+    constexpr int QX = L::QX, NR = split3_row<LY, LZ, K>(1);  // the largest part
     static_assert(BCX == BCX_WRAP, "the split step is built for compact rows");
     const int i = (z * p.ny + y) * p.nx + x;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
@@ -511,9 +570,9 @@ __device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y,
     const uint32_t h = storage_hash<ST>(p.seed, i, y);
     float v[NR][QX];
     float rw[2];
-    wall_rates3<LX, LY, LZ, ST, BCX, BCY, INTERIOR>(p, rs, xa, y, z, rw);
-    unroll<kSplit3>([&](auto G) {
-        constexpr int R0 = split3_row<LY, LZ>(G), R1 = split3_row<LY, LZ>(G + 1);
+    wall_rates3<LX, LY, LZ, ST, BCX, BCY, INTERIOR, true>(p, rs, xa, x, y, z, rw);
+    unroll<K>([&](auto G) {
+        constexpr int R0 = split3_row<LY, LZ, K>(G), R1 = split3_row<LY, LZ, K>(G + 1);
         if (g == G) {
             unroll_from<R0, R1>([&](auto Rr) {
                 constexpr int r = Rr;
@@ -522,17 +581,21 @@ __device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y,
             float m[4];
             moments3_rows<LX, LY, LZ, R0, R1>([&](auto Rr, auto A) -> float & { return v[(int)Rr - R0][(int)A]; },
                                               m[0], m[1], m[2], m[3]);
-            for (int k = 0; k < 4; ++k) xch[G][k][lane] = m[k];
+            for (int k = 0; k < 4; ++k) xch[wave][k][lane] = m[k];
         }
     });
     __syncthreads();
+    const int w0 = wave - g;  // first wave of the group
     float m[4];
-    for (int k = 0; k < 4; ++k) m[k] = ((xch[0][k][lane] + xch[1][k][lane]) + xch[2][k][lane]) + xch[3][k][lane];
+    for (int k = 0; k < 4; ++k) {
+        m[k] = xch[w0][k][lane];
+        for (int j = 1; j < K; ++j) m[k] += xch[w0 + j][k][lane];
+    }
     const float rho = L::shifted ? kShift3<LX, LY, LZ>.sum + m[0] : m[0];
     const float inv = 1.0f / rho;
     const uint32_t off = (uint32_t)((z * p.ny + y) * p.nxp + x) * (uint32_t)L::EB;
-    unroll<kSplit3>([&](auto G) {
-        constexpr int R0 = split3_row<LY, LZ>(G), R1 = split3_row<LY, LZ>(G + 1);
+    unroll<K>([&](auto G) {
+        constexpr int R0 = split3_row<LY, LZ, K>(G), R1 = split3_row<LY, LZ, K>(G + 1);
         if (g == G) {
             auto at = [&](auto Rr, auto A) -> float & { return v[(int)Rr - R0][(int)A]; };
             Eq3<LX, LY, LZ, R0, R1> e;
@@ -553,38 +616,41 @@ __device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y,
     });
 }
 
-// One step of a split lattice: 64 nodes per block, node j of the block in
-// lane j of each of its four waves.  Periodic y: every node alike.  Walls:
-// the first blocks (a multiple of 8) take the rows next to the walls, the
-// others the interior rows.  Lanes past the last node step an in-bounds node
-// of their set and store nothing (every wave must reach the barrier).
+// One step of a split lattice: kBlock / K nodes per block, node j of the
+// block in lane j % 64 of waves K (j / 64) .. K (j / 64) + K - 1.  Periodic
+// y: every node alike.  Walls: the first blocks (a multiple of 8) take the
+// rows next to the walls (wall factors from the pre-pass), the others the
+// interior rows.  Lanes past the last node step an in-bounds node of their
+// set and store nothing (every wave must reach the barrier).  Two waves per
+// SIMD asked of the register allocator (three fit at 343 velocities).
 template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void step3_split_kernel(KArgs p)
 {
-    constexpr int R = Axis<LY>::vmax;
-    __shared__ float xch[kSplit3][4][64];
-    const int g = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    constexpr int K = split3_waves<LX, LY, LZ, ST>(), NB = kBlock / K, R = Axis<LY>::vmax;
+    __shared__ float xch[kBlock / 64][4][64];
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, g = wave % K;
+    const int slot = (wave / K) * 64 + lane;
     int x = 0, y = 0, z = 0;
     if constexpr (BCY != BCY_WALL) {
-        const int j = tile_index(p) * kSplit3Nodes + lane;
+        const int j = tile_index(p) * NB + slot;
         const bool valid = j < p.nodes;
         if (valid) node_xyz(p, j, x, y, z);
-        split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, lane);
+        split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, wave, lane);
     } else {
-        const int wb = wall_blocks3_split<LY>(p.nx, p.nz);
+        const int wb = wall_blocks3<LY>(p.nx, p.nz, NB);
         const int b = blockIdx.x;
         if (b < wb) {
-            const bool valid = row_set_node3<LY, ROWS_WALLS>(p, b * kSplit3Nodes + lane, x, y, z);
+            const bool valid = row_set_node3<LY, ROWS_WALLS>(p, b * NB + slot, x, y, z);
             if (!valid) x = y = z = 0;
-            split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, lane);
+            split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, wave, lane);
         } else {
-            const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * kSplit3Nodes + lane;
+            const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * NB + slot;
             const bool valid = row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z);
             if (!valid) {
                 x = z = 0;
                 y = R;
             }
-            split3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, g, x, y, z, valid, xch, lane);
+            split3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, g, x, y, z, valid, xch, wave, lane);
         }
     }
 }
@@ -634,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void observe3_kernel(KArgs p)
             });
         });
     } else {
-        pull3<LX, LY, LZ, ST, BCX, BCY>(p, rs, xa, y, z, v);
+        pull3<LX, LY, LZ, ST, BCX, BCY>(p, rs, xa, x, y, z, v);
     }
     double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     unroll<L::QZ>([&](auto C) {

@@ -13,23 +13,24 @@ template <int LX, int LY, int LZ, int ST, int BCX, int BCY>
 struct Launchers3 {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
-        if constexpr (split3<LX, LY, LZ, ST>()) {
-            // each node over four waves (64 nodes per block)
-            constexpr int R = Axis<LY>::vmax;
-            int blocks = (a.nodes + kSplit3Nodes - 1) / kSplit3Nodes;
-            if constexpr (BCY == BCY_WALL)
-                blocks = wall_blocks3_split<LY>(a.nx, a.nz) +
-                         (a.nz * (a.ny - 2 * R) * a.nx + kSplit3Nodes - 1) / kSplit3Nodes;
-            hipLaunchKernelGGL((step3_split_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(blocks), dim3(kBlock), 0, s, a);
-            return hipGetLastError();
-        }
+        constexpr int R = Axis<LY>::vmax;
+        constexpr int NB = kBlock / split3_waves<LX, LY, LZ, ST>();  // nodes per block
         if constexpr (BCY == BCY_WALL) {
-            // the wall rows in the first blocks, then the interior rows
-            constexpr int R = Axis<LY>::vmax;
+            // the wall factors of every column, then the wall rows in the
+            // first blocks of the step and the interior rows in the others
+            if (!a.wrate) return hipErrorInvalidValue;
+            const int cols = a.nx * a.nz;
+            hipLaunchKernelGGL((wall_rate3_kernel<LX, LY, LZ, ST, BCX>), dim3((cols + kBlock - 1) / kBlock),
+                               dim3(kBlock), 0, s, a);
             const int interior = a.nz * (a.ny - 2 * R) * a.nx;
-            grid = wall_blocks3<LY>(a.nx, a.nz) + (interior + kBlock - 1) / kBlock;
+            grid = wall_blocks3<LY>(a.nx, a.nz, NB) + (interior + NB - 1) / NB;
+        } else {
+            grid = (a.nodes + NB - 1) / NB;
         }
-        hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        if constexpr (split3<LX, LY, LZ, ST>())
+            hipLaunchKernelGGL((step3_split_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((step3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(grid), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
     static hipError_t observe(const KArgs &a, int grid, hipStream_t s)
@@ -51,7 +52,7 @@ struct Launchers3 {
     static hipError_t batch(int rows, const BatchTile *tiles, int ntiles, int block, const KArgs *args,
                             const int32_t *phase, const int64_t *t0, const int64_t *bstep, int launch, hipStream_t s)
     {
-        static_assert(!split3<LX, LY, LZ, ST>(), "split lattices have no batched step");
+        static_assert(split3_waves<LX, LY, LZ, ST>() <= 2, "no batched step above 144 velocities");
         if (rows != ROWS_ALL || block > kBlock) return hipErrorInvalidValue;
         hipLaunchKernelGGL((batch_step3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(ntiles), dim3(block), 0, s, tiles, args,
                            phase, t0, bstep, launch);
@@ -65,8 +66,9 @@ struct Launchers3 {
         v->init = &init;
         v->stats = &stats;
         // no resident form: three-dimensional members are tiled; no batched
-        // form of the split lattices
-        if constexpr (!split3<LX, LY, LZ, ST>()) v->batch = &batch;
+        // form of the lattices split over four waves (their one-lane node
+        // code would live in scratch memory)
+        if constexpr (split3_waves<LX, LY, LZ, ST>() <= 2) v->batch = &batch;
     }
 };
 

@@ -91,6 +91,12 @@ def test_required_bytes_counts_both_buffers_and_the_statistics():
     assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (2048 + 1)
     c = glbm.make_config(1, 3, 0, 2000, 1, kn=0.01, bc_x="eq_ends")
     assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (8 + 1)
+    # three dimensions with walls: plus the bottom and top wall factor of
+    # every (x, z) column
+    c = glbm.make_config(3, 1, 3, 256, 128, kn=0.1, bc_y="wall", level_z=1, nz=128)
+    assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (2048 + 1) + 4 * 2 * 256 * 128
+    c = glbm.make_config(3, 1, 3, 256, 128, tau=0.8, level_z=1, nz=128)
+    assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (2048 + 1)
     bad = glbm.make_config(4, 1)
     assert glbm.load().glbm_required_bytes(ctypes.byref(bad)) == 0
 
