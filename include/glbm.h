@@ -157,9 +157,11 @@ size_t glbm_population_bytes(const glbm_config *cfg);
 /* Device bytes a solver of cfg occupies in total: its two population buffers
  * (caller-owned), the FP64 statistics buffers the library allocates on the
  * first glbm_stats call (a fixed number of partial-sum rows, at most
- * 2048 x 13 doubles) and, for a three-dimensional lattice with walls, the
- * per-column wall factors the library allocates at glbm_create (2 nx nz
- * floats); 0 if cfg is invalid.  For HBM-budget admission. */
+ * 2048 x 13 doubles) and, for the lattices with walls whose step starts
+ * with a wall pre-pass (three dimensions; the symmetric G-D1Q(2N+2) products
+ * at N = 6, 7), the per-column wall factors the library allocates at
+ * glbm_create (2 nx nz floats, nz = 1 in two dimensions); 0 if cfg is
+ * invalid.  For HBM-budget admission. */
 size_t glbm_required_bytes(const glbm_config *cfg);
 
 /* Create a solver over caller-owned device buffers pop_a and pop_b, each of
@@ -169,8 +171,8 @@ size_t glbm_required_bytes(const glbm_config *cfg);
  * nu = theta tau, section 5.2: tau = Kn H / sqrt(2 theta)); the collision
  * frequency of Eq. maineq01 is 1 / (tau + 1/2).  The state is undefined until
  * glbm_init_fields or glbm_init_populations.  *out receives the handle; the
- * caller keeps the buffers alive until glbm_destroy.  A three-dimensional
- * lattice with walls allocates its wall factors here (see
+ * caller keeps the buffers alive until glbm_destroy.  The lattices whose
+ * step takes a wall pre-pass allocate their wall factors here (see
  * glbm_required_bytes); nothing else is allocated before glbm_stats.
  * Errors: GLBM_ERR_INVALID for a bad configuration (including omega outside
  * (0, 2), ny < 2 Ny with walls, walls combined with equilibrium ends, a

@@ -234,7 +234,7 @@ struct glbm_solver {
     KArgs base;
     int grid;
     double *d_partials, *d_out, *h_out;
-    float *d_wrate;  // three-dimensional walls: per-column wall factors of a step
+    float *d_wrate;  // walls: per-column wall factors of a step
     int device;
     bool in_batch;
 };
@@ -263,18 +263,29 @@ static size_t stats_bytes(int64_t nodes)
     return sizeof(double) * kNumStats * ((size_t)stat_blocks(nodes) + 1);
 }
 
-// Bytes of the wall factors of a three-dimensional lattice with walls (the
-// bottom and top factor of every (x, z) column), 0 otherwise.
-static size_t wrate_bytes(const glbm_config *cfg, const Geometry &g)
+// The kernel variant of a valid configuration (its step is null if not built).
+static const Variant *variant_of(const glbm_config *cfg, const Geometry &g)
 {
-    return cfg->dims == 3 && cfg->bc_y == GLBM_BC_WALL ? 2 * sizeof(float) * (size_t)(g.nx * g.nz) : 0;
+    std::call_once(g_once, register_all);
+    const int bcy = cfg->dims >= 2 ? cfg->bc_y : GLBM_BC_PERIODIC;
+    return cfg->dims == 3 ? variant3_slot(g.x.code, g.y.code, g.z.code, cfg->storage, g.bcx, bcy)
+                          : variant_slot(g.x.code, g.y.code, cfg->storage, g.bcx, bcy);
+}
+
+// Bytes of the wall factors of a variant whose step reads them (the bottom
+// and top factor of every column (x, z), written by the wall pre-pass of a
+// step: three-dimensional lattices and the largest symmetric ones with
+// walls), 0 otherwise.
+static size_t wrate_bytes(const Variant *v, const Geometry &g)
+{
+    return v->wall_rates ? 2 * sizeof(float) * (size_t)(g.nx * g.nz) : 0;
 }
 
 size_t glbm_required_bytes(const glbm_config *cfg)
 {
     Geometry g;
     if (check_config(cfg, &g) != GLBM_OK) return 0;
-    return 2 * (size_t)g.buf_bytes + stats_bytes(g.nx * g.ny * g.nz) + wrate_bytes(cfg, g);
+    return 2 * (size_t)g.buf_bytes + stats_bytes(g.nx * g.ny * g.nz) + wrate_bytes(variant_of(cfg, g), g);
 }
 
 int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, glbm_t **out)
@@ -297,10 +308,8 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
     const double omega = 1.0 / (tau + 0.5);
     if (!(omega > 0.0 && omega < 2.0)) return fail(GLBM_ERR_INVALID, "collision frequency %g outside (0, 2)", omega);
 
-    std::call_once(g_once, register_all);
     const int bcy = cfg->dims >= 2 ? cfg->bc_y : GLBM_BC_PERIODIC;
-    const Variant *v = cfg->dims == 3 ? variant3_slot(g.x.code, g.y.code, g.z.code, cfg->storage, g.bcx, bcy)
-                                      : variant_slot(g.x.code, g.y.code, cfg->storage, g.bcx, bcy);
+    const Variant *v = variant_of(cfg, g);
     if (!v->step)
         return fail(GLBM_ERR_UNSUPPORTED, "no kernels built for axes (%s%d, %s%d, %s%d) with these boundaries",
                     g.x.even ? "even " : "", g.x.N, g.y.even ? "even " : "", g.y.N, g.z.even ? "even " : "", g.z.N);
@@ -352,7 +361,7 @@ int glbm_create(const glbm_config *cfg, void *pop_a, void *pop_b, void *stream, 
         a.uw[side] = (float)U;
     }
 
-    if (const size_t wb = wrate_bytes(cfg, g)) {
+    if (const size_t wb = wrate_bytes(v, g)) {
         hipError_t e = hipMalloc((void **)&h->d_wrate, wb);
         if (e != hipSuccess) {
             delete h;

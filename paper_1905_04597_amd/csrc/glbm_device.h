@@ -334,8 +334,8 @@ struct KArgs {
     const float *i_rho, *i_ux, *i_uy, *i_f;
     const float *i_uz;    // three dimensions
     void *dst2;           // init: buffer receiving f(0)
-    // three-dimensional walls: the wall factors of this step per (x, z)
-    // column, bottom [nz][nx] then top, from the wall pre-pass
+    // walls: the wall factors of this step per column (x, z), bottom [nz][nx]
+    // then top (nz = 1 in two dimensions), from the wall pre-pass
     float *wrate;
 };
 
@@ -516,23 +516,52 @@ __device__ __forceinline__ float wall_absorbed(const KArgs &p, rsrc_t rs, const 
     return s;
 }
 
+// Wall re-emission factor of column x: rho_w / (J+ sum_a fw_a), J+ the mass
+// the FP32 emission tables give out per unit wall density.
+template <int LX, int LY, int ST, int BCX, bool BOTTOM>
+__device__ __forceinline__ float wall_factor(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa)
+{
+    constexpr double jp = half_flux_f32<LY>();
+    return wall_absorbed<LX, LY, ST, BCX, BOTTOM>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[BOTTOM ? 0 : 1]);
+}
+
+// Whether the single-lattice step with walls reads the wall factors from a
+// pre-pass (wall_rate_kernel: once per column) rather than have every lane of
+// the 2R wall rows sum its column (QX R (R + 1) / 2 loads): where the wall
+// rows are a one-wave launch of their own (split lattices, above 144
+// velocities) and that sum is at least twice the node's own loads, i.e. the
+// symmetric G-D1Q(2N+2) products at N = 6 and 7 (G-D2Q256: 1920 loads per
+// wall-row lane against 256; 1829 -> 1707 us in FP32, 1300 -> 1081 us in
+// BF16).  Elsewhere the sums mostly hit L2 next to a wave-rich launch, and
+// the extra launch per step measured 2-8% slower (D1Q3 x G-D1Q(2N+2),
+// N = 2..12).
+template <int LX, int LY, int ST>
+constexpr bool wall_prepass()
+{
+    return Lat<LX, LY, ST>::Q > 144 && Axis<LY>::vmax * (Axis<LY>::vmax + 1) >= 4 * Axis<LY>::Q;
+}
+
 // Pre-collision populations of node (x, y) at the new time: pulled from the
 // source buffer, or emitted by a wall where the source row is outside.
 // INTERIOR: the node is at least the fastest y velocity away from both walls,
-// so nothing is emitted into it and the pull has no branches.
-template <int LX, int LY, int ST, int BCX, int BCY, bool INTERIOR = false>
-__device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int y,
+// so nothing is emitted into it and the pull has no branches.  PRE: the wall
+// factors of column x come from the pre-pass of this step (the same
+// arithmetic).
+template <int LX, int LY, int ST, int BCX, int BCY, bool INTERIOR = false, bool PRE = false>
+__device__ __forceinline__ void pull(const KArgs &p, rsrc_t rs, const XAddr<LX, Elem<ST>::bytes, BCX> &xa, int x, int y,
                                      float (&v)[Axis<LY>::Q][Axis<LX>::Q])
 {
     using L = Lat<LX, LY, ST>;
     float rw[2] = {0.0f, 0.0f};
     if constexpr (BCY == BCY_WALL && !INTERIOR) {
-        // the mass the FP32 emission tables give out per unit wall density
-        constexpr double jp = half_flux_f32<LY>();
         constexpr int reach = Axis<LY>::vmax;  // rows that take wall emission
-        if (y < reach) rw[0] = wall_absorbed<LX, LY, ST, BCX, true>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[0]);
-        if (y >= p.ny - reach)
-            rw[1] = wall_absorbed<LX, LY, ST, BCX, false>(p, rs, xa, nullptr) / (float)(jp * p.fwsum[1]);
+        if constexpr (PRE) {
+            if (y < reach) rw[0] = p.wrate[x];
+            if (y >= p.ny - reach) rw[1] = p.wrate[p.nx + x];
+        } else {
+            if (y < reach) rw[0] = wall_factor<LX, LY, ST, BCX, true>(p, rs, xa);
+            if (y >= p.ny - reach) rw[1] = wall_factor<LX, LY, ST, BCX, false>(p, rs, xa);
+        }
     }
     unroll<L::QY>([&](auto B) {
         constexpr int b = B, cb = Axis<LY>::c(b);
@@ -922,7 +951,9 @@ enum StepRows { ROWS_ALL = 0, ROWS_INTERIOR = 1, ROWS_WALLS = 2 };
 // lattice are a separate launch (ROWS_WALLS, FP32 registers, so that emitted
 // populations enter the collision unrounded), which keeps the packed
 // kernel's register allocation its own.
-template <int LX, int LY, int ST, int BCX, int BCY, int ROWS>
+// PRE: wall factors from the wall pre-pass (single-lattice launches of the
+// lattices with wall_prepass).
+template <int LX, int LY, int ST, int BCX, int BCY, int ROWS, bool PRE = false>
 __device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
 {
     using L = Lat<LX, LY, ST>;
@@ -935,7 +966,7 @@ __device__ __forceinline__ void step_node(const KArgs &p, int i, uint32_t seed)
     } else {
         float v[L::QY][L::QX];
         const XAddr<LX, L::EB, BCX> xa(x, p.nx);
-        pull<LX, LY, ST, BCX, BCY, ROWS == ROWS_INTERIOR>(p, rs, xa, y, v);
+        pull<LX, LY, ST, BCX, BCY, ROWS == ROWS_INTERIOR, PRE>(p, rs, xa, x, y, v);
         FloatRegs<LX, LY> regs{v};
         float rho, jx, jy, ux, uy;
         density_velocity<LX, LY, ST>(regs, rho, jx, jy, ux, uy);
@@ -1086,7 +1117,21 @@ step_kernel(KArgs p)
 {
     const int i = row_set_node<LY, ROWS>(tile_index(p) * kBlock + (int)threadIdx.x, p.nx, p.ny);
     if (i < 0) return;
-    step_node<LX, LY, ST, BCX, BCY, ROWS>(p, i, p.seed);
+    step_node<LX, LY, ST, BCX, BCY, ROWS, BCY == BCY_WALL && wall_prepass<LX, LY, ST>()>(p, i, p.seed);
+}
+
+// Wall pre-pass of a single-lattice step with walls (wall_prepass): the
+// bottom and top wall factors of every column into p.wrate ([nx] each), one
+// lane per column.
+template <int LX, int LY, int ST, int BCX>
+__global__ __launch_bounds__(kBlock) void wall_rate_kernel(KArgs p)
+{
+    const int x = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (x >= p.nx) return;
+    const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
+    const XAddr<LX, Elem<ST>::bytes, BCX> xa(x, p.nx);
+    p.wrate[x] = wall_factor<LX, LY, ST, BCX, true>(p, rs, xa);
+    p.wrate[p.nx + x] = wall_factor<LX, LY, ST, BCX, false>(p, rs, xa);
 }
 
 // Blocks of the wall rows in a merged 16-bit launch (a multiple of 8).
@@ -1147,7 +1192,7 @@ step_kernel_rows(KArgs p)
         const int wb = wall_blocks<LY>(p.nx);
         if (b < wb) {
             const int i = row_set_node<LY, ROWS_WALLS>(b * kBlock + (int)threadIdx.x, p.nx, p.ny);
-            if (i >= 0) step_node<LX, LY, ST, BCX, BCY, ROWS_WALLS>(p, i, p.seed);
+            if (i >= 0) step_node<LX, LY, ST, BCX, BCY, ROWS_WALLS, wall_prepass<LX, LY, ST>()>(p, i, p.seed);
             return;
         }
         b -= wb;
@@ -1332,7 +1377,7 @@ __global__ __launch_bounds__(kBlock) void observe_kernel(KArgs p)
             });
         });
     } else {
-        pull<LX, LY, ST, BCX, BCY>(p, rs, xa, y, v);
+        pull<LX, LY, ST, BCX, BCY>(p, rs, xa, x, y, v);
     }
     double r = 0.0, jx = 0.0, jy = 0.0;
     unroll<L::QY>([&](auto B) {

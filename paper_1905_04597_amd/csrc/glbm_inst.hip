@@ -16,6 +16,12 @@ template <int LX, int LY, int ST, int BCX, int BCY>
 struct Launchers {
     static hipError_t step(const KArgs &a, int grid, hipStream_t s)
     {
+        if constexpr (BCY == BCY_WALL && wall_prepass<LX, LY, ST>()) {
+            // the wall factors of every column first (the wall rows read them)
+            if (!a.wrate) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((wall_rate_kernel<LX, LY, ST, BCX>), dim3((a.nx + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                               s, a);
+        }
         if constexpr (BCY == BCY_PERIODIC && BCX == BCX_WRAP && split_node<LX, LY, ST>()) {
             // more than 144 velocities: each node split over a wave pair
             const int nodes = a.nx * a.ny;
@@ -130,6 +136,7 @@ struct Launchers {
         v->batch = &batch;
         v->resident = &resident;
         v->split_rows = Elem<ST>::bytes == 2 && BCY == BCY_WALL;
+        v->wall_rates = BCY == BCY_WALL && wall_prepass<LX, LY, ST>();
     }
 };
 

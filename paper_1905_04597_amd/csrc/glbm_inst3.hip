@@ -65,6 +65,7 @@ struct Launchers3 {
         v->observe = &observe;
         v->init = &init;
         v->stats = &stats;
+        v->wall_rates = BCY == BCY_WALL;
         // no resident form: three-dimensional members are tiled; no batched
         // form of the lattices split over four waves (their one-lane node
         // code would live in scratch memory)

@@ -29,6 +29,7 @@ struct Variant {
     LaunchBatch batch = nullptr;
     LaunchResident resident = nullptr;
     bool split_rows = false;  // steps run as interior rows + wall rows (16-bit storage with walls)
+    bool wall_rates = false;  // the step reads per-column wall factors from a buffer of the solver
 };
 
 // Registry of built variants, indexed by axis codes (see Axis), storage, bc_x

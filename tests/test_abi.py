@@ -91,8 +91,11 @@ def test_required_bytes_counts_both_buffers_and_the_statistics():
     assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (2048 + 1)
     c = glbm.make_config(1, 3, 0, 2000, 1, kn=0.01, bc_x="eq_ends")
     assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (8 + 1)
-    # three dimensions with walls: plus the bottom and top wall factor of
-    # every (x, z) column
+    # lattices whose step starts with a wall pre-pass (three dimensions, the
+    # symmetric G-D1Q(2N+2) products at N = 6 and 7, with walls): plus a wall
+    # factor per (x, z) column and wall
+    c = glbm.make_config(2, 7, 7, 1024, 64, kn=0.1, bc_y="wall", even_x=True, even_y=True)
+    assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (256 + 1) + 4 * 2 * 1024
     c = glbm.make_config(3, 1, 3, 256, 128, kn=0.1, bc_y="wall", level_z=1, nz=128)
     assert glbm.required_bytes(c) == 2 * glbm.population_bytes(c) + 8 * 13 * (2048 + 1) + 4 * 2 * 256 * 128
     c = glbm.make_config(3, 1, 3, 256, 128, tau=0.8, level_z=1, nz=128)
