@@ -1121,17 +1121,21 @@ step_kernel(KArgs p)
 }
 
 // Wall pre-pass of a single-lattice step with walls (wall_prepass): the
-// bottom and top wall factors of every column into p.wrate ([nx] each), one
-// lane per column.
+// bottom and top wall factors of every column into p.wrate ([nx] each).  A
+// block takes kBlock / 2 columns, its first two waves the bottom wall and the
+// other two the top one.
 template <int LX, int LY, int ST, int BCX>
 __global__ __launch_bounds__(kBlock) void wall_rate_kernel(KArgs p)
 {
-    const int x = blockIdx.x * kBlock + (int)threadIdx.x;
+    const int x = blockIdx.x * (kBlock / 2) + ((int)threadIdx.x & (kBlock / 2 - 1));
+    const bool top = (int)threadIdx.x >= kBlock / 2;
     if (x >= p.nx) return;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const XAddr<LX, Elem<ST>::bytes, BCX> xa(x, p.nx);
-    p.wrate[x] = wall_factor<LX, LY, ST, BCX, true>(p, rs, xa);
-    p.wrate[p.nx + x] = wall_factor<LX, LY, ST, BCX, false>(p, rs, xa);
+    if (top)
+        p.wrate[p.nx + x] = wall_factor<LX, LY, ST, BCX, false>(p, rs, xa);
+    else
+        p.wrate[x] = wall_factor<LX, LY, ST, BCX, true>(p, rs, xa);
 }
 
 // Blocks of the wall rows in a merged 16-bit launch (a multiple of 8).

@@ -394,7 +394,12 @@ __host__ __device__ constexpr int wall_blocks3(int nx, int nz, int nb)
 // Above 125 velocities a node's populations and the collision do not fit one
 // lane's registers at two waves per SIMD (at 126-144 the compiler spilled to
 // accumulation registers and ran one wave; the 343 of G-D3Q343 do not fit at
-// all), so the step splits each node over split3_waves waves of a block:
+// all), so the step splits each node over split3_waves waves of a block (for
+// 16-bit storage, which holds FP32 working values of half the bytes in
+// flight, also where halves lift the kernel from two to three waves per
+// SIMD: 81-99 velocities, measured 0.50 -> 0.51-0.54 of 8 TB/s; at 108-125
+// the halves stay at two waves and the split's repeated work cost 0.09-0.14,
+// and above 125 four parts beat two, 0.37-0.43 -> 0.43-0.46):
 // wave g holds the velocity rows [split3_row(g), split3_row(g + 1)) of its
 // nodes (row r = c QY + b, QX populations each), pulls, sums, relaxes and
 // stores only those; the partial sums of mass and momentum meet in LDS and
@@ -405,7 +410,9 @@ __host__ __device__ constexpr int wall_blocks3(int nx, int nz, int nb)
 template <int LX, int LY, int LZ, int ST>
 constexpr int split3_waves()
 {
-    return Lat3<LX, LY, LZ, ST>::Q > 144 ? 4 : Lat3<LX, LY, LZ, ST>::Q > 125 ? 2 : 1;
+    constexpr int Q = Lat3<LX, LY, LZ, ST>::Q;
+    if constexpr (Elem<ST>::bytes == 2) return Q > 125 ? 4 : (Q > 63 && Q <= 99) ? 2 : 1;
+    return Q > 144 ? 4 : Q > 125 ? 2 : 1;
 }
 template <int LX, int LY, int LZ, int ST>
 constexpr bool split3()
@@ -507,18 +514,22 @@ __device__ __forceinline__ bool row_set_node3(const KArgs &p, int j, int &x, int
 }
 
 // Wall pre-pass of a step with walls: the bottom and top wall factors of
-// every (x, z) column into p.wrate, one lane per column (the wall rows of
-// the step then read them instead of each summing its column).
+// every (x, z) column into p.wrate (the wall rows of the step then read them
+// instead of each summing its column).  A block takes kBlock / 2 columns,
+// its first two waves the bottom wall and the other two the top one.
 template <int LX, int LY, int LZ, int ST, int BCX>
 __global__ __launch_bounds__(kBlock) void wall_rate3_kernel(KArgs p)
 {
-    const int col = blockIdx.x * kBlock + (int)threadIdx.x;
+    const int col = blockIdx.x * (kBlock / 2) + ((int)threadIdx.x & (kBlock / 2 - 1));
+    const bool top = (int)threadIdx.x >= kBlock / 2;
     if (col >= p.nx * p.nz) return;
     const int z = col / p.nx, x = col - z * p.nx;
     const rsrc_t rs = make_rsrc(p.src, p.buf_bytes);
     const XAddr<LX, Elem<ST>::bytes, BCX> xa(x, p.nx);
-    p.wrate[col] = wall_factor3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z);
-    p.wrate[p.nx * p.nz + col] = wall_factor3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z);
+    if (top)
+        p.wrate[p.nx * p.nz + col] = wall_factor3<LX, LY, LZ, ST, BCX, false>(p, rs, xa, z);
+    else
+        p.wrate[col] = wall_factor3<LX, LY, LZ, ST, BCX, true>(p, rs, xa, z);
 }
 
 // One step.  Periodic y: every node alike.  Walls: one launch whose first

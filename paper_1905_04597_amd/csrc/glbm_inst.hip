@@ -19,8 +19,8 @@ struct Launchers {
         if constexpr (BCY == BCY_WALL && wall_prepass<LX, LY, ST>()) {
             // the wall factors of every column first (the wall rows read them)
             if (!a.wrate) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((wall_rate_kernel<LX, LY, ST, BCX>), dim3((a.nx + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                               s, a);
+            hipLaunchKernelGGL((wall_rate_kernel<LX, LY, ST, BCX>), dim3((a.nx + kBlock / 2 - 1) / (kBlock / 2)),
+                               dim3(kBlock), 0, s, a);
         }
         if constexpr (BCY == BCY_PERIODIC && BCX == BCX_WRAP && split_node<LX, LY, ST>()) {
             // more than 144 velocities: each node split over a wave pair

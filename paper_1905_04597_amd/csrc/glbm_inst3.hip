@@ -20,7 +20,7 @@ struct Launchers3 {
             // first blocks of the step and the interior rows in the others
             if (!a.wrate) return hipErrorInvalidValue;
             const int cols = a.nx * a.nz;
-            hipLaunchKernelGGL((wall_rate3_kernel<LX, LY, LZ, ST, BCX>), dim3((cols + kBlock - 1) / kBlock),
+            hipLaunchKernelGGL((wall_rate3_kernel<LX, LY, LZ, ST, BCX>), dim3((cols + kBlock / 2 - 1) / (kBlock / 2)),
                                dim3(kBlock), 0, s, a);
             const int interior = a.nz * (a.ny - 2 * R) * a.nx;
             grid = wall_blocks3<LY>(a.nx, a.nz, NB) + (interior + NB - 1) / NB;
@@ -52,7 +52,7 @@ struct Launchers3 {
     static hipError_t batch(int rows, const BatchTile *tiles, int ntiles, int block, const KArgs *args,
                             const int32_t *phase, const int64_t *t0, const int64_t *bstep, int launch, hipStream_t s)
     {
-        static_assert(split3_waves<LX, LY, LZ, ST>() <= 2, "no batched step above 144 velocities");
+        static_assert(Lat3<LX, LY, LZ, ST>::Q <= 144, "no batched step above 144 velocities");
         if (rows != ROWS_ALL || block > kBlock) return hipErrorInvalidValue;
         hipLaunchKernelGGL((batch_step3_kernel<LX, LY, LZ, ST, BCX, BCY>), dim3(ntiles), dim3(block), 0, s, tiles, args,
                            phase, t0, bstep, launch);
@@ -67,9 +67,9 @@ struct Launchers3 {
         v->stats = &stats;
         v->wall_rates = BCY == BCY_WALL;
         // no resident form: three-dimensional members are tiled; no batched
-        // form of the lattices split over four waves (their one-lane node
-        // code would live in scratch memory)
-        if constexpr (split3_waves<LX, LY, LZ, ST>() <= 2) v->batch = &batch;
+        // form above 144 velocities (the one-lane node code would live in
+        // scratch memory)
+        if constexpr (Lat3<LX, LY, LZ, ST>::Q <= 144) v->batch = &batch;
     }
 };
 
