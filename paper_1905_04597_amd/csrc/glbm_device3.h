@@ -229,44 +229,84 @@ struct Eq3 {
     float dm, hx, hy, hz;
 };
 
+// The per-axis FP64 equilibrium tables of a node: F_a(u_x), F_b(u_y), F_c(u_z)
+// at unit density.
+template <int LX, int LY, int LZ>
+__device__ __forceinline__ void eq3_tables(float ux, float uy, float uz, double (&Fx)[Axis<LX>::Q],
+                                           double (&Fy)[Axis<LY>::Q], double (&Fz)[Axis<LZ>::Q])
+{
+    axis_equilibrium<LX, double>((double)ux, Fx);
+    axis_equilibrium<LY, double>((double)uy, Fy);
+    axis_equilibrium<LZ, double>((double)uz, Fz);
+}
+
+// The defect corrections dm, hx, hy, hz from the tables: the mass and
+// momentum that the FP32 factors rho F_a and F_b F_c miss, summed in FP64
+// over every row.
+template <int LX, int LY, int LZ, class TX, class TY, class TZ>
+__device__ __forceinline__ void eq3_defects(float rho, float jx, float jy, float jz, const TX &Fx, const TY &Fy,
+                                            const TZ &Fz, float (&d)[4])
+{
+    constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q, QZ = Axis<LZ>::Q;
+    double sx = 0.0, mx = 0.0, syz = 0.0, my = 0.0, mz = 0.0;
+    unroll<QX>([&](auto A) {
+        constexpr int a = A, ca = Axis<LX>::c(a);
+        const float rF = (float)((double)rho * Fx(a));
+        sx += (double)rF;
+        mx += (double)ca * (double)rF;
+    });
+    unroll<QZ>([&](auto C) {
+        constexpr int c = C, cc = Axis<LZ>::c(c);
+        unroll<QY>([&](auto B) {
+            constexpr int b = B, cb = Axis<LY>::c(b);
+            const float fyz = (float)(Fy(b) * Fz(c));
+            syz += (double)fyz;
+            my += (double)cb * (double)fyz;
+            mz += (double)cc * (double)fyz;
+        });
+    });
+    constexpr int nxm = Axis<LX>::cmin ? 2 : 1, nym = Axis<LY>::cmin ? 2 : 1, nzm = Axis<LZ>::cmin ? 2 : 1;
+    d[0] = (float)(sx * syz - (double)rho) * (1.0f / (nxm * nym * nzm));
+    d[1] = (float)(0.5 * (mx * syz - (double)jx)) * (1.0f / (nym * nzm));
+    d[2] = (float)(0.5 * (sx * my - (double)jy)) * (1.0f / (nxm * nzm));
+    d[3] = (float)(0.5 * (sx * mz - (double)jz)) * (1.0f / (nxm * nym));
+}
+
+// The FP32 factors of the rows [R0, R1) from the tables.
+template <int LX, int LY, int LZ, int R0, int R1, class TX, class TY, class TZ>
+__device__ __forceinline__ void eq3_rows(const KArgs &p, float rho, const TX &Fx, const TY &Fy, const TZ &Fz,
+                                         Eq3<LX, LY, LZ, R0, R1> &e)
+{
+    constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q;
+    unroll<QX>([&](auto A) {
+        constexpr int a = A, ca = Axis<LX>::c(a);
+        e.rF[a] = (float)((double)rho * Fx(a));
+        e.gK[a] = p.gth * (float)(kRest<LX>.w[a] * ca);
+    });
+    unroll_from<R0, R1>([&](auto Rr) {
+        constexpr int r = Rr, c = r / QY, b = r % QY;
+        e.FYZ[r - R0] = (float)(Fy(b) * Fz(c));
+    });
+}
+
+// All factors of a collision of the rows [R0, R1) (one lane computes the whole
+// node's tables and defects).
 template <int LX, int LY, int LZ, int R0, int R1>
 __device__ __forceinline__ void eq3_factors(const KArgs &p, float rho, float jx, float jy, float jz, float ux, float uy,
                                             float uz, Eq3<LX, LY, LZ, R0, R1> &e)
 {
-    constexpr int QX = Axis<LX>::Q, QY = Axis<LY>::Q, QZ = Axis<LZ>::Q;
-    double sx = 0.0, mx = 0.0, syz = 0.0, my = 0.0, mz = 0.0;
-    {
-        double Fd[QX];
-        axis_equilibrium<LX, double>((double)ux, Fd);
-        unroll<QX>([&](auto A) {
-            constexpr int a = A, ca = Axis<LX>::c(a);
-            e.rF[a] = (float)((double)rho * Fd[a]);
-            sx += (double)e.rF[a];
-            mx += (double)ca * (double)e.rF[a];
-            e.gK[a] = p.gth * (float)(kRest<LX>.w[a] * ca);
-        });
-    }
-    {
-        double Fy[QY], Fz[QZ];
-        axis_equilibrium<LY, double>((double)uy, Fy);
-        axis_equilibrium<LZ, double>((double)uz, Fz);
-        unroll<QZ>([&](auto C) {
-            constexpr int c = C, cc = Axis<LZ>::c(c);
-            unroll<QY>([&](auto B) {
-                constexpr int b = B, cb = Axis<LY>::c(b), r = c * QY + b;
-                const float fyz = (float)(Fy[b] * Fz[c]);
-                if constexpr (r >= R0 && r < R1) e.FYZ[r - R0] = fyz;
-                syz += (double)fyz;
-                my += (double)cb * (double)fyz;
-                mz += (double)cc * (double)fyz;
-            });
-        });
-    }
-    constexpr int nxm = Axis<LX>::cmin ? 2 : 1, nym = Axis<LY>::cmin ? 2 : 1, nzm = Axis<LZ>::cmin ? 2 : 1;
-    e.dm = (float)(sx * syz - (double)rho) * (1.0f / (nxm * nym * nzm));
-    e.hx = (float)(0.5 * (mx * syz - (double)jx)) * (1.0f / (nym * nzm));
-    e.hy = (float)(0.5 * (sx * my - (double)jy)) * (1.0f / (nxm * nzm));
-    e.hz = (float)(0.5 * (sx * mz - (double)jz)) * (1.0f / (nxm * nym));
+    double Fx[Axis<LX>::Q], Fy[Axis<LY>::Q], Fz[Axis<LZ>::Q];
+    eq3_tables<LX, LY, LZ>(ux, uy, uz, Fx, Fy, Fz);
+    auto fx = [&](int a) { return Fx[a]; };
+    auto fy = [&](int b) { return Fy[b]; };
+    auto fz = [&](int c) { return Fz[c]; };
+    float d[4];
+    eq3_defects<LX, LY, LZ>(rho, jx, jy, jz, fx, fy, fz, d);
+    e.dm = d[0];
+    e.hx = d[1];
+    e.hy = d[2];
+    e.hz = d[3];
+    eq3_rows<LX, LY, LZ, R0, R1>(p, rho, fx, fy, fz, e);
 }
 
 // BGK relaxation with the linear force (section 5.4) of the velocity rows
@@ -403,10 +443,13 @@ __host__ __device__ constexpr int wall_blocks3(int nx, int nz, int nb)
 // wave g holds the velocity rows [split3_row(g), split3_row(g + 1)) of its
 // nodes (row r = c QY + b, QX populations each), pulls, sums, relaxes and
 // stores only those; the partial sums of mass and momentum meet in LDS and
-// are added in wave order.  Each wave forms the equilibrium factors of the
-// whole node (cheap next to the populations).  The one-lane node code (the
-// batched step) adds the same partial sums in the same order, so a node
-// gives the same bits split or not.
+// are added in wave order.  The first wave of each node's group then forms
+// the node's FP64 axis tables and defect corrections, shared through LDS
+// behind a second barrier (formed by every wave they were a third of the
+// VALU work of a 16-bit split step, which is VALU-bound), and each wave its
+// rows' FP32 factors from them.  The one-lane node code (the batched step)
+// adds the same partial sums in the same order and forms the same tables,
+// so a node gives the same bits split or not.
 template <int LX, int LY, int LZ, int ST>
 constexpr int split3_waves()
 {
@@ -566,9 +609,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // the exchange slot of its wave, then (after the block's barrier, which
 // every wave reaches once) the node's moments from the K slots of its wave
 // group, its rows relaxed and, for a valid node, stored.
-template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR>
+// Per-node tables of a split step shared through LDS: the FP64 axis tables
+// (QX + QY + QZ entries) and the four defect corrections of each node of
+// the block, computed once by the first wave of the node's group.
+template <int LX, int LY, int LZ, int NB>
+struct SplitTables3 {
+    static constexpr int NT = Axis<LX>::Q + Axis<LY>::Q + Axis<LZ>::Q;
+    double tab[NT][NB];
+    float def[4][NB];
+};
+
+template <int LX, int LY, int LZ, int ST, int BCX, int BCY, bool INTERIOR, int NB>
 __device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y, int z, bool valid,
-                                            float (&xch)[kBlock / 64][4][64], int wave, int lane)
+                                            float (&xch)[kBlock / 64][4][64], SplitTables3<LX, LY, LZ, NB> &sh,
+                                            int slot, int wave, int lane)
 {
     using L = Lat3<LX, LY, LZ, ST>;
     constexpr int K = split3_waves<LX, LY, LZ, ST>();
@@ -605,12 +659,35 @@ __device__ __forceinline__ void split3_node(const KArgs &p, int g, int x, int y,
     const float rho = L::shifted ? kShift3<LX, LY, LZ>.sum + m[0] : m[0];
     const float inv = 1.0f / rho;
     const uint32_t off = (uint32_t)((z * p.ny + y) * p.nxp + x) * (uint32_t)L::EB;
+    // the node's FP64 tables and defects, once per node (the first wave of
+    // its group), shared through LDS: the same arithmetic as eq3_factors
+    constexpr int QY = L::QY, QZ = L::QZ;
+    if (g == 0) {
+        double Fx[QX], Fy[QY], Fz[QZ];
+        eq3_tables<LX, LY, LZ>(m[1] * inv, m[2] * inv, m[3] * inv, Fx, Fy, Fz);
+        float d[4];
+        eq3_defects<LX, LY, LZ>(
+            rho, m[1], m[2], m[3], [&](int a) { return Fx[a]; }, [&](int b) { return Fy[b]; },
+            [&](int c) { return Fz[c]; }, d);
+        for (int j = 0; j < QX; ++j) sh.tab[j][slot] = Fx[j];
+        for (int j = 0; j < QY; ++j) sh.tab[QX + j][slot] = Fy[j];
+        for (int j = 0; j < QZ; ++j) sh.tab[QX + QY + j][slot] = Fz[j];
+        for (int k = 0; k < 4; ++k) sh.def[k][slot] = d[k];
+    }
+    __syncthreads();
+    auto fx = [&](int a) { return sh.tab[a][slot]; };
+    auto fy = [&](int b) { return sh.tab[QX + b][slot]; };
+    auto fz = [&](int c) { return sh.tab[QX + QY + c][slot]; };
     unroll<K>([&](auto G) {
         constexpr int R0 = split3_row<LY, LZ, K>(G), R1 = split3_row<LY, LZ, K>(G + 1);
         if (g == G) {
             auto at = [&](auto Rr, auto A) -> float & { return v[(int)Rr - R0][(int)A]; };
             Eq3<LX, LY, LZ, R0, R1> e;
-            eq3_factors<LX, LY, LZ, R0, R1>(p, rho, m[1], m[2], m[3], m[1] * inv, m[2] * inv, m[3] * inv, e);
+            eq3_rows<LX, LY, LZ, R0, R1>(p, rho, fx, fy, fz, e);
+            e.dm = sh.def[0][slot];
+            e.hx = sh.def[1][slot];
+            e.hy = sh.def[2][slot];
+            e.hz = sh.def[3][slot];
             relax3_rows<LX, LY, LZ, ST, R0, R1>(p, e, at, mix32(h));
             if (valid) {
                 unroll_from<R0, R1>([&](auto Rr) {
@@ -639,6 +716,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 {
     constexpr int K = split3_waves<LX, LY, LZ, ST>(), NB = kBlock / K, R = Axis<LY>::vmax;
     __shared__ float xch[kBlock / 64][4][64];
+    __shared__ SplitTables3<LX, LY, LZ, NB> sh;
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, g = wave % K;
     const int slot = (wave / K) * 64 + lane;
     int x = 0, y = 0, z = 0;
@@ -646,14 +724,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         const int j = tile_index(p) * NB + slot;
         const bool valid = j < p.nodes;
         if (valid) node_xyz(p, j, x, y, z);
-        split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, wave, lane);
+        split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, sh, slot, wave, lane);
     } else {
         const int wb = wall_blocks3<LY>(p.nx, p.nz, NB);
         const int b = blockIdx.x;
         if (b < wb) {
             const bool valid = row_set_node3<LY, ROWS_WALLS>(p, b * NB + slot, x, y, z);
             if (!valid) x = y = z = 0;
-            split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, wave, lane);
+            split3_node<LX, LY, LZ, ST, BCX, BCY, false>(p, g, x, y, z, valid, xch, sh, slot, wave, lane);
         } else {
             const int j = tile_of(b - wb, gridDim.x - wb, p.remap) * NB + slot;
             const bool valid = row_set_node3<LY, ROWS_INTERIOR>(p, j, x, y, z);
@@ -661,7 +739,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                 x = z = 0;
                 y = R;
             }
-            split3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, g, x, y, z, valid, xch, wave, lane);
+            split3_node<LX, LY, LZ, ST, BCX, BCY, true>(p, g, x, y, z, valid, xch, sh, slot, wave, lane);
         }
     }
 }
