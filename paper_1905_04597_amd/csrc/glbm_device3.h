@@ -434,12 +434,11 @@ __host__ __device__ constexpr int wall_blocks3(int nx, int nz, int nb)
 // Above 125 velocities a node's populations and the collision do not fit one
 // lane's registers at two waves per SIMD (at 126-144 the compiler spilled to
 // accumulation registers and ran one wave; the 343 of G-D3Q343 do not fit at
-// all), so the step splits each node over split3_waves waves of a block (for
-// 16-bit storage, which holds FP32 working values of half the bytes in
-// flight, also where halves lift the kernel from two to three waves per
-// SIMD: 81-99 velocities, measured 0.50 -> 0.51-0.54 of 8 TB/s; at 108-125
-// the halves stay at two waves and the split's repeated work cost 0.09-0.14,
-// and above 125 four parts beat two, 0.37-0.43 -> 0.43-0.46):
+// all), so the step splits each node over split3_waves waves of a block:
+// two from 100 velocities on in FP32 (neutral there: the step is
+// memory-bound) and from 64 on in 16-bit storage (whose step is VALU-bound:
+// three waves per SIMD instead of two, 0.48-0.52 -> 0.55-0.59 of 8 TB/s at
+// 108-125 velocities); four above 144 (FP32) or 125 (16-bit):
 // wave g holds the velocity rows [split3_row(g), split3_row(g + 1)) of its
 // nodes (row r = c QY + b, QX populations each), pulls, sums, relaxes and
 // stores only those; the partial sums of mass and momentum meet in LDS and
@@ -454,8 +453,8 @@ template <int LX, int LY, int LZ, int ST>
 constexpr int split3_waves()
 {
     constexpr int Q = Lat3<LX, LY, LZ, ST>::Q;
-    if constexpr (Elem<ST>::bytes == 2) return Q > 125 ? 4 : (Q > 63 && Q <= 99) ? 2 : 1;
-    return Q > 144 ? 4 : Q > 125 ? 2 : 1;
+    if constexpr (Elem<ST>::bytes == 2) return Q > 125 ? 4 : Q > 63 ? 2 : 1;
+    return Q > 144 ? 4 : Q > 99 ? 2 : 1;
 }
 template <int LX, int LY, int LZ, int ST>
 constexpr bool split3()
