@@ -438,7 +438,8 @@ __host__ __device__ constexpr int wall_blocks3(int nx, int nz, int nb)
 // two from 100 velocities on in FP32 (neutral there: the step is
 // memory-bound) and from 64 on in 16-bit storage (whose step is VALU-bound:
 // three waves per SIMD instead of two, 0.48-0.52 -> 0.55-0.59 of 8 TB/s at
-// 108-125 velocities); four above 144 (FP32) or 125 (16-bit):
+// 108-125 velocities; at 126-144 two waves per node beat four, 0.45-0.49 ->
+// 0.49-0.56); four above 144:
 // wave g holds the velocity rows [split3_row(g), split3_row(g + 1)) of its
 // nodes (row r = c QY + b, QX populations each), pulls, sums, relaxes and
 // stores only those; the partial sums of mass and momentum meet in LDS and
@@ -453,7 +454,7 @@ template <int LX, int LY, int LZ, int ST>
 constexpr int split3_waves()
 {
     constexpr int Q = Lat3<LX, LY, LZ, ST>::Q;
-    if constexpr (Elem<ST>::bytes == 2) return Q > 125 ? 4 : Q > 63 ? 2 : 1;
+    if constexpr (Elem<ST>::bytes == 2) return Q > 144 ? 4 : Q > 63 ? 2 : 1;
     return Q > 144 ? 4 : Q > 99 ? 2 : 1;
 }
 template <int LX, int LY, int LZ, int ST>
