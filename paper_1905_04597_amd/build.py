@@ -63,29 +63,35 @@ def _compile(args):
     return obj
 
 
-def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def tasks():
+    """(source, object, defines) of every object of the library, slowest first."""
     # the three-dimensional objects are among the slowest: start them first
-    tasks = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3_%d.o" % k), ["-DGLBM_3D_PART=%d" % k])
+    out = [(os.path.join(CSRC, "glbm_inst3.hip"), os.path.join(BUILD, "glbm_inst3_%d.o" % k), ["-DGLBM_3D_PART=%d" % k])
              for k in (8, 7, 6, 5, 4, 0, 1, 2, 3)]
-    tasks.append((os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), []))
-    tasks.append((os.path.join(CSRC, "glbm_probe.hip"), os.path.join(BUILD, "glbm_probe.o"), []))
+    out.append((os.path.join(CSRC, "glbm_api.hip"), os.path.join(BUILD, "glbm_api.o"), []))
+    out.append((os.path.join(CSRC, "glbm_probe.hip"), os.path.join(BUILD, "glbm_probe.o"), []))
     for lv in LEVELS:
         for even in (0, 1):
             # one-dimensional; two-dimensional periodic y (or mixed); symmetric with walls
             for compact, walls in ((0, 0), (1, 0), (1, 1)):
                 if lv == 0 and (not compact or walls):
                     continue  # the mixed lattices: two-dimensional, one object
-                tasks.append((os.path.join(CSRC, "glbm_inst.hip"),
+                out.append((os.path.join(CSRC, "glbm_inst.hip"),
                               os.path.join(BUILD, "glbm_inst_%s%d%s.o" % ("e" if even else "", lv,
                                                                          ("cw" if walls else "c") if compact else "")),
                               ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_EVEN=%d" % even, "-DGLBM_COMPACT=%d" % compact,
                                "-DGLBM_WALLS=%d" % walls]))
     # levels 8..13: the mixed channel lattice D1Q3 x G-D1Q(2N+2) only
     for lv in MIXED_LEVELS:
-        tasks.insert(2, (os.path.join(CSRC, "glbm_inst.hip"), os.path.join(BUILD, "glbm_inst_e%dc.o" % lv),
+        out.insert(2, (os.path.join(CSRC, "glbm_inst.hip"), os.path.join(BUILD, "glbm_inst_e%dc.o" % lv),
                          ["-DGLBM_LEVEL=%d" % lv, "-DGLBM_EVEN=1", "-DGLBM_COMPACT=1"]))
-    todo = [t for t in tasks if not incremental or _stale(t[0], t[1])]
+    return out
+
+
+def build(jobs: int | None = None, incremental: bool = False, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = tasks()
+    todo = [t for t in objs if not incremental or _stale(t[0], t[1])]
     jobs = jobs or min(len(todo) or 1, os.cpu_count() or 4, 16)
     if todo:
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -93,7 +99,7 @@ def build(jobs: int | None = None, incremental: bool = False, verbose: bool = Fa
                 if verbose:
                     print("built", os.path.relpath(obj, HERE), flush=True)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [t[1] for t in tasks]
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [t[1] for t in objs]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
